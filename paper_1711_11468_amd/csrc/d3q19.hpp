@@ -1,0 +1,150 @@
+// d3q19.hpp - device-side D3Q19 velocity set, storage formats and the TRT
+// collision with split body forcing.
+//
+// The model (paper Sect. 2: D3Q19, two-relaxation-time collision, bounce-back;
+// Sect. 2.1: constant body force) with the standard formulas:
+//   rho = sum_i f_i,  u = (sum_i c_i f_i + g/2) / rho
+//   e_i = w_i rho [1 + 3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u]
+//   F_i = w_i [3 (c_i - u) + 9 (c_i.u) c_i] . g
+//   f*_i = f_i - (f+_i - e+_i)/tau+ - (f-_i - e-_i)/tau-
+//          + (1 - 1/(2 tau+)) F+_i + (1 - 1/(2 tau-)) F-_i
+// where x+_i = (x_i + x_opp(i))/2 and x-_i = (x_i - x_opp(i))/2, and
+// tau- = 1/2 + Lambda/(tau+ - 1/2).
+//
+// Velocity order: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 diagonals, each
+// opposite pair adjacent (i odd, i+1), so opp(i) = i+1 for odd i >= 1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lbm.h"
+
+namespace lbm {
+
+constexpr int Q = 19;
+
+struct Vel {
+  static constexpr int cx[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int cy[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int cz[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  static constexpr int opp[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+};
+
+__host__ __device__ constexpr double weight(int i) {
+  return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// ---- storage formats ------------------------------------------------------
+// R: arithmetic type of the collision; T: element type in memory.
+// Shifted formats store h_i = f_i - w_i (scaled by 2^s for half precision)
+// and run the collision on h directly.
+struct StoreF64 {
+  using T = double;
+  using R = double;
+  static constexpr bool kShifted = false;
+  __device__ __forceinline__ static R load(T v, R) { return v; }
+  __device__ __forceinline__ static T store(R v, R) { return v; }
+};
+
+struct StoreF32Shifted {
+  using T = float;
+  using R = float;
+  static constexpr bool kShifted = true;
+  __device__ __forceinline__ static R load(T v, R) { return v; }
+  __device__ __forceinline__ static T store(R v, R) { return v; }
+};
+
+struct StoreF16Shifted {
+  using T = _Float16;
+  using R = float;
+  static constexpr bool kShifted = true;
+  // scale = 2^s on store, 2^-s on load: exact (power of two), so the only
+  // rounding is the float -> half conversion (round to nearest even).
+  __device__ __forceinline__ static R load(T v, R inv_scale) { return (R)v * inv_scale; }
+  __device__ __forceinline__ static T store(R v, R scale) { return (T)(v * scale); }
+};
+
+// Collision constants in the arithmetic type.
+template <typename R>
+struct Collide {
+  R lp, lm;          // 1/tau+, 1/tau-
+  R ap, am;          // 1 - 1/(2 tau+), 1 - 1/(2 tau-)
+  R gx, gy, gz;      // body-force density
+  R scale, inv_scale;  // storage scale (half precision only), else 1
+};
+
+// In-place TRT collision of one fluid node.  SHIFTED: f holds h = f - w.
+template <typename R, bool SHIFTED>
+__device__ __forceinline__ void trt_collide(R (&f)[Q], const Collide<R>& k) {
+  R s = f[0];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) s += f[i];
+  const R rho = SHIFTED ? R(1) + s : s;
+  R jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+  for (int i = 1; i < Q; i += 2) {
+    const R d = f[i] - f[i + 1];
+    if (Vel::cx[i] != 0) jx += Vel::cx[i] > 0 ? d : -d;
+    if (Vel::cy[i] != 0) jy += Vel::cy[i] > 0 ? d : -d;
+    if (Vel::cz[i] != 0) jz += Vel::cz[i] > 0 ? d : -d;
+  }
+  const R inv_rho = R(1) / rho;
+  const R ux = (jx + R(0.5) * k.gx) * inv_rho;
+  const R uy = (jy + R(0.5) * k.gy) * inv_rho;
+  const R uz = (jz + R(0.5) * k.gz) * inv_rho;
+  const R usq = ux * ux + uy * uy + uz * uz;
+  const R ug = ux * k.gx + uy * k.gy + uz * k.gz;
+  // e_i - (SHIFTED ? w_i : 0) = w_i (s + rho (3 cu + 9/2 cu^2 - 3/2 usq))
+  {
+    const R w = R(weight(0));
+    const R e0 = w * (s - R(1.5) * rho * usq);
+    const R F0 = w * (R(-3) * ug);
+    f[0] = f[0] + k.lp * (e0 - f[0]) + k.ap * F0;
+  }
+#pragma unroll
+  for (int i = 1; i < Q; i += 2) {
+    const R w = R(weight(i));
+    const R cu = R(Vel::cx[i]) * ux + R(Vel::cy[i]) * uy + R(Vel::cz[i]) * uz;
+    const R cg = R(Vel::cx[i]) * k.gx + R(Vel::cy[i]) * k.gy + R(Vel::cz[i]) * k.gz;
+    const R ep = w * (s + rho * (R(4.5) * cu * cu - R(1.5) * usq));
+    const R em = w * (R(3) * rho * cu);
+    const R Fp = w * (R(9) * cu * cg - R(3) * ug);
+    const R Fm = w * (R(3) * cg);
+    const R fp = R(0.5) * (f[i] + f[i + 1]);
+    const R fm = R(0.5) * (f[i] - f[i + 1]);
+    const R sym = k.lp * (ep - fp) + k.ap * Fp;
+    const R asym = k.lm * (em - fm) + k.am * Fm;
+    f[i] = f[i] + sym + asym;
+    f[i + 1] = f[i + 1] + sym - asym;
+  }
+}
+
+// Density and velocity of a (pre-collision, unshifted) node in double.
+__device__ __forceinline__ void moments_f64(const double (&f)[Q], double gx, double gy,
+                                            double gz, double& rho, double& ux,
+                                            double& uy, double& uz, double& jx,
+                                            double& jy, double& jz) {
+  double s = f[0];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) s += f[i];
+  jx = jy = jz = 0.0;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    jx += Vel::cx[i] * f[i];
+    jy += Vel::cy[i] * f[i];
+    jz += Vel::cz[i] * f[i];
+  }
+  rho = s;
+  ux = (jx + 0.5 * gx) / rho;
+  uy = (jy + 0.5 * gy) / rho;
+  uz = (jz + 0.5 * gz) / rho;
+}
+
+// Periodic neighbour coordinate v - c for c in {-1, 0, 1}.
+__device__ __forceinline__ int wrap_sub(int v, int c, int n) {
+  int r = v - c;
+  return r < 0 ? r + n : (r >= n ? r - n : r);
+}
+
+}  // namespace lbm

@@ -1,0 +1,158 @@
+// gather.hpp - node-wise access to the canonical (pre-collision) state held
+// in a pull buffer, shared by the I/O and diagnostics kernels.
+//
+// A pull buffer holds post-collision populations.  The canonical state of a
+// node is what one streaming pass delivers to it: population i comes from
+// the neighbour x - c_i (periodic wrap), or, under half-way bounce-back when
+// that neighbour is solid, from the node's own opposite slot.  For the list
+// representation the adjacency list already encodes exactly this.
+#pragma once
+
+#include "d3q19.hpp"
+
+namespace lbm {
+
+struct View {
+  int nx, ny, nz;
+  int64_t stride;
+  const uint8_t* mask;
+  const int32_t* adj;
+  const int32_t* node_map;
+  const int32_t* fluid_index;
+  float scale, inv_scale;  // half-precision storage scale (else 1)
+};
+
+template <int LAYOUT>
+__device__ __forceinline__ int64_t vslot(int64_t n, int i, int64_t stride) {
+  return LAYOUT == LBM_SOA ? (int64_t)i * stride + n : n * Q + i;
+}
+
+__device__ __forceinline__ int64_t wrap_node(const View& v, int x, int y, int z) {
+  x = x < 0 ? x + v.nx : (x >= v.nx ? x - v.nx : x);
+  y = y < 0 ? y + v.ny : (y >= v.ny ? y - v.ny : y);
+  z = z < 0 ? z + v.nz : (z >= v.nz ? z - v.nz : z);
+  return (int64_t)x + (int64_t)v.nx * ((int64_t)y + (int64_t)v.ny * z);
+}
+
+__device__ __forceinline__ void node_xyz(const View& v, int64_t n, int& x, int& y, int& z) {
+  x = (int)(n % v.nx);
+  const int64_t r = n / v.nx;
+  y = (int)(r % v.ny);
+  z = (int)(r / v.ny);
+}
+
+template <class ST>
+__device__ __forceinline__ double to_f64(typename ST::T raw, int i, const View& v) {
+  if (ST::kShifted) return (double)ST::load(raw, v.inv_scale) + weight(i);
+  return (double)raw;
+}
+
+template <class ST>
+__device__ __forceinline__ typename ST::T from_f64(double f, int i, const View& v) {
+  using T = typename ST::T;
+  if (ST::kShifted) return (T)((f - weight(i)) * (double)v.scale);
+  return (T)f;
+}
+
+// The storage value of the rest state f_i = w_i.
+template <class ST>
+__device__ __forceinline__ typename ST::T rest_value(int i) {
+  using T = typename ST::T;
+  return ST::kShifted ? (T)0 : (T)weight(i);
+}
+
+// Canonical populations of full node index `node`; false if it holds none
+// (solid under half-way bounce-back).
+template <class ST, int LAYOUT, int ADDR, int BB>
+__device__ __forceinline__ bool gather_canonical(const typename ST::T* __restrict__ src,
+                                                 const View& v, int64_t node, double (&f)[Q]) {
+  if (ADDR == LBM_LIST) {
+    const int m = v.node_map[node];
+    if (m < 0) return false;
+    f[0] = to_f64<ST>(src[m], 0, v);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) f[i] = to_f64<ST>(src[v.adj[(int64_t)(i - 1) * v.stride + m]], i, v);
+    return true;
+  }
+  const bool solid = v.mask[node] != 0;
+  if (BB == LBM_HALFWAY && solid) return false;
+  int x, y, z;
+  node_xyz(v, node, x, y, z);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int64_t sn = wrap_node(v, x - Vel::cx[i], y - Vel::cy[i], z - Vel::cz[i]);
+    int64_t at = vslot<LAYOUT>(sn, i, v.stride);
+    if (BB == LBM_HALFWAY && i != 0 && v.mask[sn] != 0) at = vslot<LAYOUT>(node, Vel::opp[i], v.stride);
+    f[i] = to_f64<ST>(src[at], i, v);
+  }
+  return true;
+}
+
+// e_i(rho, u) - w_i in double.
+__device__ __forceinline__ double eq_shifted(int i, double rho, double ux, double uy, double uz) {
+  const double cu = Vel::cx[i] * ux + Vel::cy[i] * uy + Vel::cz[i] * uz;
+  const double usq = ux * ux + uy * uy + uz * uz;
+  return weight(i) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
+}
+
+// Fixed-order block reduction of NV doubles: wavefront shuffles, then the
+// per-wave results combined by thread 0 in wave order.  Slots whose bit is
+// set in max_mask combine with fmax, the others with +.  Result valid in
+// thread 0.  blockDim.x must be a multiple of 64, at most 1024.
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&a)[NV], uint32_t max_mask) {
+  __shared__ double sm[16][NV];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int s = 0; s < NV; ++s) {
+      const double o = __shfl_down(a[s], off, 64);
+      a[s] = ((max_mask >> s) & 1u) ? fmax(a[s], o) : a[s] + o;
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int s = 0; s < NV; ++s) sm[wid][s] = a[s];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+    for (int w = 1; w < nw; ++w) {
+#pragma unroll
+      for (int s = 0; s < NV; ++s)
+        a[s] = ((max_mask >> s) & 1u) ? fmax(a[s], sm[w][s]) : a[s] + sm[w][s];
+    }
+  }
+}
+
+}  // namespace lbm
+
+#include <type_traits>
+
+namespace lbm {
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// Call f(storage_tag, layout, addressing, bounce) with compile-time tags for
+// the parameter combination of p (LIST implies SOA and half-way).
+template <class F>
+hipError_t dispatch(const lbm_params& p, F&& f) {
+  auto by_store = [&](auto st) -> hipError_t {
+    if (p.addressing == LBM_LIST) return f(st, IC<LBM_SOA>{}, IC<LBM_LIST>{}, IC<LBM_HALFWAY>{});
+    if (p.layout == LBM_SOA) {
+      if (p.bounce == LBM_FULLWAY) return f(st, IC<LBM_SOA>{}, IC<LBM_DIRECT>{}, IC<LBM_FULLWAY>{});
+      return f(st, IC<LBM_SOA>{}, IC<LBM_DIRECT>{}, IC<LBM_HALFWAY>{});
+    }
+    if (p.bounce == LBM_FULLWAY) return f(st, IC<LBM_AOS>{}, IC<LBM_DIRECT>{}, IC<LBM_FULLWAY>{});
+    return f(st, IC<LBM_AOS>{}, IC<LBM_DIRECT>{}, IC<LBM_HALFWAY>{});
+  };
+  switch (p.storage) {
+    case LBM_F64: return by_store(StoreF64{});
+    case LBM_F32_SHIFTED: return by_store(StoreF32Shifted{});
+    default: return by_store(StoreF16Shifted{});
+  }
+}
+
+}  // namespace lbm

@@ -1,0 +1,51 @@
+// internal.hpp - host-side context record and kernel launcher declarations
+// shared by the translation units of the library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lbm.h"
+
+struct lbm_ctx {
+  lbm_params p;
+  lbm_sizes s;
+  lbm_buffers b;
+  hipStream_t stream;
+  int cur;             // index of the buffer holding the current state
+  int64_t step;        // updates since init
+  int u_prev_valid;    // u_prev holds the velocity of a previous call
+  int block;           // threads per workgroup for the sweeps
+  int device;
+};
+
+namespace lbm {
+
+void set_error(const char* fmt, ...);
+
+inline void* pdf_buf(lbm_ctx* c, int which) { return which == 0 ? c->b.pdf_a : c->b.pdf_b; }
+
+// Launchers: each enqueues on c->stream and returns a hipError_t.
+hipError_t launch_sweep(lbm_ctx* c, const void* src, void* dst);
+hipError_t launch_fill_rest(lbm_ctx* c, void* buf);
+hipError_t launch_build_adjacency(lbm_ctx* c);
+hipError_t launch_export(lbm_ctx* c, const void* src, const int64_t* ids_dev, int64_t count,
+                         double* out_dev);
+hipError_t launch_import(lbm_ctx* c, const double* canon_dev, void* dst);
+hipError_t launch_init_fields(lbm_ctx* c, const double* rho_dev, const double* u_dev, void* dst);
+// Moments + block partials; then a one-block fixed-order final reduction
+// into partials[0..kStatSlots).  residual_mode: 0 none, 1 compute.
+constexpr int kStatSlots = 12;
+hipError_t launch_moments(lbm_ctx* c, const void* src, double* rho_out, double* u_out,
+                          int residual_mode, double* partials, int64_t* n_blocks_out);
+hipError_t launch_verify(lbm_ctx* c, const void* src, int kind, const double* ref_dev,
+                         double* partials, int64_t* n_blocks_out);
+hipError_t launch_final_reduce(lbm_ctx* c, double* partials, int64_t n_blocks, int n_slots,
+                               uint32_t max_mask, double* out_dev);
+// Slot layouts of the two reductions.
+enum { M_MASS = 0, M_PX, M_PY, M_PZ, M_DU2, M_U2, M_UMAX, M_NONFINITE, M_COUNT };
+enum { V_MAXABS = 0, V_ERR2, V_REF2, V_REFMAX, V_COUNT_N, V_COUNT };
+hipError_t launch_membench(int kind, const double* a, double* b, int64_t n, int64_t stride,
+                           int block, hipStream_t stream);
+
+}  // namespace lbm

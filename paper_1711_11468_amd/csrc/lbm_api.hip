@@ -1,0 +1,406 @@
+// lbm_api.hip - host runtime behind the C ABI declared in include/lbm.h:
+// parameter validation, sizing, geometry set-up (fluid-node compaction on
+// the host, adjacency on the device), the step loop with A/B buffer swap,
+// diagnostics, verification and canonical state transfer.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "d3q19.hpp"
+#include "internal.hpp"
+
+namespace lbm {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+
+static int hip_fail(hipError_t e, const char* what) {
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return LBM_EDEVICE;
+}
+
+#define LBM_HIP(call, what)                 \
+  do {                                      \
+    hipError_t e_ = (call);                 \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+static int elem_size(int storage) {
+  return storage == LBM_F64 ? 8 : (storage == LBM_F32_SHIFTED ? 4 : 2);
+}
+
+static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+static int validate(const lbm_params* p) {
+  if (!p) { set_error("params is NULL"); return LBM_EINVAL; }
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) { set_error("dimensions must be >= 1"); return LBM_EINVAL; }
+  if ((int64_t)p->ny * p->nz > 0x7fffffffLL) { set_error("ny*nz too large"); return LBM_EOVERFLOW; }
+  if (!(p->tau_plus > 0.5)) { set_error("tau_plus must exceed 1/2"); return LBM_EINVAL; }
+  if (!(p->magic_lambda > 0.0)) { set_error("magic_lambda must be positive"); return LBM_EINVAL; }
+  if (p->layout != LBM_SOA && p->layout != LBM_AOS) { set_error("bad layout"); return LBM_EINVAL; }
+  if (p->addressing != LBM_DIRECT && p->addressing != LBM_LIST) { set_error("bad addressing"); return LBM_EINVAL; }
+  if (p->storage < LBM_F64 || p->storage > LBM_F16_SHIFTED) { set_error("bad storage"); return LBM_EINVAL; }
+  if (p->bounce != LBM_FULLWAY && p->bounce != LBM_HALFWAY) { set_error("bad bounce"); return LBM_EINVAL; }
+  if (p->addressing == LBM_LIST && (p->layout != LBM_SOA || p->bounce != LBM_HALFWAY)) {
+    set_error("list addressing requires SOA layout and half-way bounce-back");
+    return LBM_EINVAL;
+  }
+  if (p->storage == LBM_F16_SHIFTED && (p->f16_scale_log2 < 0 || p->f16_scale_log2 > 24)) {
+    set_error("f16_scale_log2 must be in [0, 24]");
+    return LBM_EINVAL;
+  }
+  if (p->block != 0 && (p->block < 64 || p->block > 1024 || p->block % 64 != 0)) {
+    set_error("block must be 0 or a multiple of 64 in [64, 1024]");
+    return LBM_EINVAL;
+  }
+  if (p->pad < -1 || p->pad > (1 << 24)) { set_error("pad must be -1 or in [0, 2^24]"); return LBM_EINVAL; }
+  for (int a = 0; a < 3; ++a)
+    if (!(p->g[a] == p->g[a]) || p->g[a] > 1e30 || p->g[a] < -1e30) { set_error("bad g"); return LBM_EINVAL; }
+  return LBM_OK;
+}
+
+static int plan_sizes(const lbm_params* p, int64_t n_fluid, lbm_sizes* s) {
+  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  if (N >= 0x7fffffffLL) { set_error("lattice of %lld nodes exceeds 32-bit node indices", (long long)N); return LBM_EOVERFLOW; }
+  const int es = elem_size(p->storage);
+  memset(s, 0, sizeof *s);
+  s->n_nodes = N;
+  s->n_fluid = n_fluid;
+  s->n_sites = p->addressing == LBM_LIST ? n_fluid : N;
+  if (p->layout == LBM_AOS) {
+    s->stride = Q;
+    s->pdf_bytes = round_up(N * Q * es, 256);
+  } else {
+    // Direction arrays start on 256-byte boundaries.  The automatic pad
+    // shifts consecutive arrays by 1 KiB when their natural spacing is a
+    // multiple of 64 KiB, so the 19 streams do not start on the same HBM
+    // channel.
+    const int64_t align = 256 / es;
+    int64_t st = round_up(s->n_sites < 1 ? 1 : s->n_sites, align);
+    if (p->pad >= 0) st += round_up(p->pad, align);
+    else if ((st * es) % 65536 == 0) st += 1024 / es;
+    s->stride = st;
+    s->pdf_bytes = st * Q * es;
+  }
+  s->mask_bytes = round_up(N, 256);
+  if (p->addressing == LBM_LIST) {
+    if (s->stride * Q >= 0x7fffffffLL) {
+      set_error("list of %lld fluid nodes overflows int32 adjacency entries", (long long)n_fluid);
+      return LBM_EOVERFLOW;
+    }
+    s->adj_bytes = round_up(s->stride * (Q - 1) * 4, 256);
+    s->fluid_index_bytes = round_up((n_fluid < 1 ? 1 : n_fluid) * 4, 256);
+    s->node_map_bytes = round_up(N * 4, 256);
+  }
+  s->u_prev_bytes = round_up(3 * (s->n_sites < 1 ? 1 : s->n_sites) * 8, 256);
+  s->scratch_bytes = round_up((int64_t)(4096 + 1) * kStatSlots * 8, 256);
+  // Algorithmic HBM bytes per site update: 19 loads + 19 stores of one
+  // element, plus the flag byte (direct) or 18 int32 adjacency entries (list).
+  s->bytes_per_update = 2.0 * Q * es + (p->addressing == LBM_LIST ? 4.0 * (Q - 1) : 1.0);
+  return LBM_OK;
+}
+
+static int64_t count_fluid(const lbm_params* p, const uint8_t* mask) {
+  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  int64_t nf = 0;
+  for (int64_t n = 0; n < N; ++n) nf += mask[n] == 0;
+  return nf;
+}
+
+static bool aligned256(const void* ptr) { return ((uintptr_t)ptr & 255u) == 0; }
+
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err; }
+
+const char* lbm_strerror(int code) {
+  switch (code) {
+    case LBM_OK: return "success";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "out of memory";
+    case LBM_EOVERFLOW: return "lattice too large for 32-bit indices";
+    case LBM_EDEVICE: return "HIP device error";
+    case LBM_ENONFINITE: return "non-finite populations";
+    case LBM_ENOTCONV: return "not converged";
+    default: return "unknown error";
+  }
+}
+
+int lbm_plan(const lbm_params* params, const uint8_t* mask_host, lbm_sizes* out) {
+  int rc = validate(params);
+  if (rc) return rc;
+  if (!mask_host || !out) { set_error("mask_host and out must be non-NULL"); return LBM_EINVAL; }
+  const int64_t N = (int64_t)params->nx * params->ny * params->nz;
+  if (N >= 0x7fffffffLL) { set_error("lattice too large"); return LBM_EOVERFLOW; }
+  return plan_sizes(params, count_fluid(params, mask_host), out);
+}
+
+int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* mask_host,
+                      const lbm_buffers* bufs, void* stream) {
+  if (!out) { set_error("out is NULL"); return LBM_EINVAL; }
+  *out = nullptr;
+  int rc = validate(params);
+  if (rc) return rc;
+  if (!mask_host || !bufs) { set_error("mask_host and bufs must be non-NULL"); return LBM_EINVAL; }
+  lbm_sizes s;
+  const int64_t N = (int64_t)params->nx * params->ny * params->nz;
+  if (N >= 0x7fffffffLL) { set_error("lattice too large"); return LBM_EOVERFLOW; }
+  rc = plan_sizes(params, count_fluid(params, mask_host), &s);
+  if (rc) return rc;
+  if (!bufs->pdf_a || !bufs->pdf_b || !bufs->mask || !bufs->scratch) {
+    set_error("pdf_a, pdf_b, mask and scratch are required");
+    return LBM_EINVAL;
+  }
+  if (!aligned256(bufs->pdf_a) || !aligned256(bufs->pdf_b)) {
+    set_error("pdf buffers must be 256-byte aligned");
+    return LBM_EINVAL;
+  }
+  if (params->addressing == LBM_LIST && (!bufs->adj || !bufs->fluid_index || !bufs->node_map)) {
+    set_error("list addressing needs adj, fluid_index and node_map");
+    return LBM_EINVAL;
+  }
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) { set_error("host allocation failed"); return LBM_ENOMEM; }
+  c->p = *params;
+  c->s = s;
+  c->b = *bufs;
+  if (params->addressing != LBM_LIST) {
+    c->b.adj = nullptr;
+    c->b.fluid_index = nullptr;
+    c->b.node_map = nullptr;
+  }
+  c->stream = (hipStream_t)stream;
+  c->cur = 0;
+  c->step = 0;
+  c->u_prev_valid = 0;
+  c->block = params->block ? params->block : 256;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) { delete c; return hip_fail(e, "hipGetDevice"); }
+
+  auto fail = [&](hipError_t err, const char* what) {
+    delete c;
+    return hip_fail(err, what);
+  };
+  e = hipMemcpyAsync(c->b.mask, mask_host, (size_t)N, hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return fail(e, "mask upload");
+  if (params->addressing == LBM_LIST) {
+    // Fluid-node vector in x-fastest order and the node -> list map.
+    std::vector<int32_t> fidx, nmap;
+    try {
+      fidx.resize((size_t)(s.n_fluid > 0 ? s.n_fluid : 1));
+      nmap.resize((size_t)N);
+    } catch (...) {
+      delete c;
+      set_error("host allocation failed");
+      return LBM_ENOMEM;
+    }
+    int32_t m = 0;
+    for (int64_t n = 0; n < N; ++n) {
+      if (mask_host[n] == 0) {
+        fidx[m] = (int32_t)n;
+        nmap[n] = m++;
+      } else {
+        nmap[n] = -1;
+      }
+    }
+    e = hipMemcpyAsync(c->b.fluid_index, fidx.data(), (size_t)s.n_fluid * 4, hipMemcpyHostToDevice,
+                       c->stream);
+    if (e != hipSuccess) return fail(e, "fluid index upload");
+    e = hipMemcpyAsync(c->b.node_map, nmap.data(), (size_t)N * 4, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return fail(e, "node map upload");
+    e = launch_build_adjacency(c);
+    if (e != hipSuccess) return fail(e, "adjacency kernel");
+    // the host vectors are released below only after the copies completed
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(e, "adjacency sync");
+  }
+  e = launch_fill_rest(c, c->b.pdf_a);
+  if (e != hipSuccess) return fail(e, "rest fill A");
+  e = launch_fill_rest(c, c->b.pdf_b);
+  if (e != hipSuccess) return fail(e, "rest fill B");
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(e, "init sync");
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm_init_fields(lbm_ctx* c, const double* rho_dev, const double* u_dev) {
+  if (!c) { set_error("ctx is NULL"); return LBM_EINVAL; }
+  LBM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  LBM_HIP(launch_init_fields(c, rho_dev, u_dev, pdf_buf(c, c->cur)), "init fields kernel");
+  LBM_HIP(hipStreamSynchronize(c->stream), "init fields sync");
+  c->step = 0;
+  c->u_prev_valid = 0;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int32_t n) {
+  if (!c || n < 0) { set_error("bad ctx or negative step count"); return LBM_EINVAL; }
+  LBM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  for (int32_t k = 0; k < n; ++k) {
+    hipError_t e = launch_sweep(c, pdf_buf(c, c->cur), pdf_buf(c, 1 - c->cur));
+    if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    c->cur = 1 - c->cur;
+    c->step += 1;
+  }
+  return LBM_OK;
+}
+
+int lbm_macroscopic(lbm_ctx* c, double* rho_dev, double* u_dev, lbm_stats* out) {
+  if (!c || !out) { set_error("ctx and out must be non-NULL"); return LBM_EINVAL; }
+  LBM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  const int64_t N = c->s.n_nodes;
+  if (rho_dev) LBM_HIP(hipMemsetAsync(rho_dev, 0, (size_t)N * 8, c->stream), "rho clear");
+  if (u_dev) LBM_HIP(hipMemsetAsync(u_dev, 0, (size_t)N * 24, c->stream), "u clear");
+  const int residual_mode = c->b.u_prev ? (c->u_prev_valid ? 2 : 1) : 0;
+  double* partials = (double*)c->b.scratch;
+  int64_t nb = 0;
+  LBM_HIP(launch_moments(c, pdf_buf(c, c->cur), rho_dev, u_dev, residual_mode, partials, &nb),
+          "moments kernel");
+  double* res_dev = partials + 4096 * kStatSlots;
+  LBM_HIP(launch_final_reduce(c, partials, nb, M_COUNT, 1u << M_UMAX, res_dev), "reduce kernel");
+  double r[kStatSlots];
+  LBM_HIP(hipMemcpyAsync(r, res_dev, sizeof(double) * M_COUNT, hipMemcpyDeviceToHost, c->stream),
+          "stats download");
+  LBM_HIP(hipStreamSynchronize(c->stream), "stats sync");
+  out->mass = r[M_MASS];
+  out->momentum[0] = r[M_PX];
+  out->momentum[1] = r[M_PY];
+  out->momentum[2] = r[M_PZ];
+  out->u_max = r[M_UMAX];
+  out->nonfinite = (int64_t)r[M_NONFINITE];
+  out->residual = residual_mode == 2 ? (r[M_U2] > 0 ? sqrt(r[M_DU2] / r[M_U2]) : (r[M_DU2] > 0 ? INFINITY : 0.0)) : -1.0;
+  out->step = c->step;
+  if (residual_mode > 0) c->u_prev_valid = 1;
+  if (out->nonfinite > 0) {
+    set_error("%lld fluid nodes hold non-finite populations", (long long)out->nonfinite);
+    return LBM_ENONFINITE;
+  }
+  return LBM_OK;
+}
+
+int lbm_verify(lbm_ctx* c, int32_t kind, const double* ref_dev, lbm_verify_result* out) {
+  if (!c || !out) { set_error("ctx and out must be non-NULL"); return LBM_EINVAL; }
+  if (kind != LBM_VERIFY_SLAB && kind != LBM_VERIFY_DUCT && kind != LBM_VERIFY_REFERENCE) {
+    set_error("unknown verification kind %d", kind);
+    return LBM_EINVAL;
+  }
+  if (kind == LBM_VERIFY_REFERENCE && !ref_dev) { set_error("reference field is NULL"); return LBM_EINVAL; }
+  if (kind == LBM_VERIFY_SLAB && c->p.nz < 3) { set_error("slab needs nz >= 3"); return LBM_EINVAL; }
+  if (kind == LBM_VERIFY_DUCT && (c->p.ny < 3 || c->p.nz < 3)) { set_error("duct needs ny, nz >= 3"); return LBM_EINVAL; }
+  LBM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  double* partials = (double*)c->b.scratch;
+  int64_t nb = 0;
+  LBM_HIP(launch_verify(c, pdf_buf(c, c->cur), kind, ref_dev, partials, &nb), "verify kernel");
+  double* res_dev = partials + 4096 * kStatSlots;
+  LBM_HIP(launch_final_reduce(c, partials, nb, V_COUNT, (1u << V_MAXABS) | (1u << V_REFMAX), res_dev),
+          "reduce kernel");
+  double r[kStatSlots];
+  LBM_HIP(hipMemcpyAsync(r, res_dev, sizeof(double) * V_COUNT, hipMemcpyDeviceToHost, c->stream),
+          "verify download");
+  LBM_HIP(hipStreamSynchronize(c->stream), "verify sync");
+  out->max_abs = r[V_MAXABS];
+  out->rel_l2 = r[V_REF2] > 0 ? sqrt(r[V_ERR2] / r[V_REF2]) : sqrt(r[V_ERR2]);
+  out->ref_max = r[V_REFMAX];
+  out->n_compared = (int64_t)r[V_COUNT_N];
+  return LBM_OK;
+}
+
+int lbm_export_pdfs(lbm_ctx* c, const int64_t* node_ids_host, int64_t count, double* out_host) {
+  if (!c || !out_host || count < 0) { set_error("bad arguments"); return LBM_EINVAL; }
+  const int64_t N = c->s.n_nodes;
+  if (!node_ids_host && count != N) { set_error("count must equal N when node_ids is NULL"); return LBM_EINVAL; }
+  if (node_ids_host) {
+    for (int64_t k = 0; k < count; ++k)
+      if (node_ids_host[k] < 0 || node_ids_host[k] >= N) {
+        set_error("node id %lld out of range", (long long)node_ids_host[k]);
+        return LBM_EINVAL;
+      }
+  }
+  if (count == 0) return LBM_OK;
+  LBM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  const int64_t chunk = count < (int64_t)(1 << 22) ? count : (int64_t)(1 << 22);
+  int64_t* ids_dev = nullptr;
+  double* out_dev = nullptr;
+  std::vector<int64_t> ids;
+  try {
+    ids.resize((size_t)chunk);
+  } catch (...) {
+    set_error("host allocation failed");
+    return LBM_ENOMEM;
+  }
+  if (hipMalloc(&ids_dev, (size_t)chunk * 8) != hipSuccess ||
+      hipMalloc(&out_dev, (size_t)chunk * Q * 8) != hipSuccess) {
+    if (ids_dev) (void)hipFree(ids_dev);
+    set_error("export scratch allocation failed");
+    return LBM_ENOMEM;
+  }
+  int rc = LBM_OK;
+  for (int64_t k0 = 0; k0 < count && rc == LBM_OK; k0 += chunk) {
+    const int64_t m = (count - k0) < chunk ? (count - k0) : chunk;
+    for (int64_t k = 0; k < m; ++k) ids[k] = node_ids_host ? node_ids_host[k0 + k] : k0 + k;
+    hipError_t e = hipMemcpyAsync(ids_dev, ids.data(), (size_t)m * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_export(c, pdf_buf(c, c->cur), ids_dev, m, out_dev);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(out_host + k0 * Q, out_dev, (size_t)m * Q * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "export");
+  }
+  (void)hipFree(ids_dev);
+  (void)hipFree(out_dev);
+  return rc;
+}
+
+int lbm_import_pdfs(lbm_ctx* c, const double* host_in) {
+  if (!c || !host_in) { set_error("bad arguments"); return LBM_EINVAL; }
+  LBM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  const size_t bytes = (size_t)c->s.n_nodes * Q * 8;
+  double* canon = nullptr;
+  if (hipMalloc(&canon, bytes) != hipSuccess) {
+    set_error("import scratch allocation of %zu bytes failed", bytes);
+    return LBM_ENOMEM;
+  }
+  hipError_t e = hipMemcpyAsync(canon, host_in, bytes, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_import(c, canon, pdf_buf(c, c->cur));
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(canon);
+  if (e != hipSuccess) return hip_fail(e, "import");
+  c->u_prev_valid = 0;
+  return LBM_OK;
+}
+
+int lbm_get_sizes(const lbm_ctx* c, lbm_sizes* out) {
+  if (!c || !out) { set_error("bad arguments"); return LBM_EINVAL; }
+  *out = c->s;
+  return LBM_OK;
+}
+
+int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->step : -1; }
+
+int lbm_current_buffer(const lbm_ctx* c) { return c ? c->cur : -1; }
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+int lbm_membench(int32_t kind, const double* a, double* b, int64_t n, int64_t stride, int32_t block,
+                 void* stream) {
+  if (kind < 0 || kind > 3 || !b || (kind != 3 && !a) || n <= 0) { set_error("bad membench arguments"); return LBM_EINVAL; }
+  if (kind != 0 && stride < n) { set_error("stride must be >= n"); return LBM_EINVAL; }
+  if (block < 64 || block > 1024 || block % 64) { set_error("bad block"); return LBM_EINVAL; }
+  LBM_HIP(launch_membench(kind, a, b, n, stride, block, (hipStream_t)stream), "membench launch");
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,183 @@
+// state_io.hip - set-up and state transfer kernels: rest-state fill,
+// adjacency-list construction (paper Sect. 3 "Lattice Representation",
+// Sect. 3.2), canonical export/import and equilibrium initialisation.
+#include "gather.hpp"
+#include "internal.hpp"
+
+namespace lbm {
+
+static View make_view(const lbm_ctx* c) {
+  View v;
+  v.nx = c->p.nx;
+  v.ny = c->p.ny;
+  v.nz = c->p.nz;
+  v.stride = c->s.stride;
+  v.mask = c->b.mask;
+  v.adj = c->b.adj;
+  v.node_map = c->b.node_map;
+  v.fluid_index = c->b.fluid_index;
+  if (c->p.storage == LBM_F16_SHIFTED) {
+    v.scale = ldexpf(1.0f, c->p.f16_scale_log2);
+    v.inv_scale = ldexpf(1.0f, -c->p.f16_scale_log2);
+  } else {
+    v.scale = v.inv_scale = 1.0f;
+  }
+  return v;
+}
+
+View view_of(const lbm_ctx* c) { return make_view(c); }
+
+static inline unsigned grid_for(int64_t n, int blk) {
+  int64_t g = (n + blk - 1) / blk;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// ---- rest state -----------------------------------------------------------
+template <class ST, int LAYOUT>
+__global__ void k_fill_rest(typename ST::T* __restrict__ buf, int64_t total, int64_t stride) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int i = LAYOUT == LBM_SOA ? (int)(e / stride) : (int)(e % Q);
+  buf[e] = rest_value<ST>(i);
+}
+
+hipError_t launch_fill_rest(lbm_ctx* c, void* buf) {
+  return dispatch(c->p, [&](auto st, auto lay, auto, auto) -> hipError_t {
+    using ST = decltype(st);
+    constexpr int L = decltype(lay)::value;
+    const int64_t total = c->s.pdf_bytes / (int64_t)sizeof(typename ST::T);
+    hipLaunchKernelGGL((k_fill_rest<ST, L>), dim3(grid_for(total, 256)), dim3(256), 0, c->stream,
+                       (typename ST::T*)buf, total, c->s.stride);
+    return hipGetLastError();
+  });
+}
+
+// ---- adjacency list -------------------------------------------------------
+// adj[(i-1)*stride + m] = slot a pull of direction i reads for list node m:
+// the neighbour's slot i*stride + map(x - c_i), or the node's own opposite
+// slot opp(i)*stride + m when the neighbour is solid (half-way bounce-back).
+__global__ void k_build_adjacency(View v, int nf, int32_t* __restrict__ adj) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nf) return;
+  int x, y, z;
+  node_xyz(v, v.fluid_index[m], x, y, z);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int64_t sn = wrap_node(v, x - Vel::cx[i], y - Vel::cy[i], z - Vel::cz[i]);
+    const int t = v.node_map[sn];
+    const int64_t s = t >= 0 ? (int64_t)i * v.stride + t : (int64_t)Vel::opp[i] * v.stride + m;
+    adj[(int64_t)(i - 1) * v.stride + m] = (int32_t)s;
+  }
+}
+
+hipError_t launch_build_adjacency(lbm_ctx* c) {
+  const int nf = (int)c->s.n_fluid;
+  if (nf == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_build_adjacency, dim3(grid_for(nf, 256)), dim3(256), 0, c->stream,
+                     make_view(c), nf, c->b.adj);
+  return hipGetLastError();
+}
+
+// ---- export ---------------------------------------------------------------
+template <class ST, int LAYOUT, int ADDR, int BB>
+__global__ void k_export(const typename ST::T* __restrict__ src, View v,
+                         const int64_t* __restrict__ ids, int64_t count, double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const int64_t node = ids[k];
+  double f[Q];
+  const bool has = gather_canonical<ST, LAYOUT, ADDR, BB>(src, v, node, f);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) out[k * Q + i] = has ? f[i] : 0.0;
+}
+
+hipError_t launch_export(lbm_ctx* c, const void* src, const int64_t* ids_dev, int64_t count,
+                         double* out_dev) {
+  return dispatch(c->p, [&](auto st, auto lay, auto addr, auto bb) -> hipError_t {
+    using ST = decltype(st);
+    hipLaunchKernelGGL((k_export<ST, decltype(lay)::value, decltype(addr)::value,
+                                 decltype(bb)::value>),
+                       dim3(grid_for(count, 256)), dim3(256), 0, c->stream,
+                       (const typename ST::T*)src, make_view(c), ids_dev, count, out_dev);
+    return hipGetLastError();
+  });
+}
+
+// ---- import and equilibrium initialisation --------------------------------
+// Both write the pull buffer Q whose streaming image is a given canonical
+// state P: Q_i(y) = P_i(y + c_i), or, under half-way bounce-back when
+// y + c_i is solid, Q_i(y) = P_opp(i)(y) (each slot has exactly one image).
+// Import reads P from a device array; init evaluates P = e(rho, u) (solids
+// under full-way bounce-back hold the rest state).
+struct CanonFromArray {
+  const double* P;
+  __device__ double operator()(int64_t node, int i, const View&) const { return P[node * Q + i]; }
+};
+
+struct CanonFromFields {
+  const double* rho;  // N or null (1)
+  const double* u;    // [3][N] or null (0)
+  int64_t n_nodes;
+  int fullway;
+  __device__ double operator()(int64_t node, int i, const View& v) const {
+    if (fullway && v.mask[node] != 0) return weight(i);
+    const double r = rho ? rho[node] : 1.0;
+    double ux = 0.0, uy = 0.0, uz = 0.0;
+    if (u) {
+      ux = u[node];
+      uy = u[n_nodes + node];
+      uz = u[2 * n_nodes + node];
+    }
+    return weight(i) + eq_shifted(i, r, ux, uy, uz);
+  }
+};
+
+template <class ST, int LAYOUT, int ADDR, int BB, class SRC>
+__global__ void k_scatter_canonical(SRC P, View v, int64_t n_sites, typename ST::T* __restrict__ dst) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_sites) return;
+  const int64_t node = ADDR == LBM_LIST ? (int64_t)v.fluid_index[s] : s;
+  const int64_t site = s;  // slot index: node (direct) or list position
+  if (ADDR == LBM_DIRECT && BB == LBM_HALFWAY && v.mask[node] != 0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dst[vslot<LAYOUT>(site, i, v.stride)] = rest_value<ST>(i);
+    return;
+  }
+  int x, y, z;
+  node_xyz(v, node, x, y, z);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int64_t tn = wrap_node(v, x + Vel::cx[i], y + Vel::cy[i], z + Vel::cz[i]);
+    double val;
+    if (BB == LBM_HALFWAY && i != 0 && v.mask[tn] != 0) val = P(node, Vel::opp[i], v);
+    else val = P(tn, i, v);
+    dst[vslot<LAYOUT>(site, i, v.stride)] = from_f64<ST>(val, i, v);
+  }
+}
+
+hipError_t launch_import(lbm_ctx* c, const double* canon_dev, void* dst) {
+  return dispatch(c->p, [&](auto st, auto lay, auto addr, auto bb) -> hipError_t {
+    using ST = decltype(st);
+    const int64_t n = c->s.n_sites;
+    hipLaunchKernelGGL((k_scatter_canonical<ST, decltype(lay)::value, decltype(addr)::value,
+                                            decltype(bb)::value, CanonFromArray>),
+                       dim3(grid_for(n, 256)), dim3(256), 0, c->stream, CanonFromArray{canon_dev},
+                       make_view(c), n, (typename ST::T*)dst);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_init_fields(lbm_ctx* c, const double* rho_dev, const double* u_dev, void* dst) {
+  return dispatch(c->p, [&](auto st, auto lay, auto addr, auto bb) -> hipError_t {
+    using ST = decltype(st);
+    const int64_t n = c->s.n_sites;
+    CanonFromFields P{rho_dev, u_dev, c->s.n_nodes, c->p.bounce == LBM_FULLWAY ? 1 : 0};
+    hipLaunchKernelGGL((k_scatter_canonical<ST, decltype(lay)::value, decltype(addr)::value,
+                                            decltype(bb)::value, CanonFromFields>),
+                       dim3(grid_for(n, 256)), dim3(256), 0, c->stream, P, make_view(c), n,
+                       (typename ST::T*)dst);
+    return hipGetLastError();
+  });
+}
+
+}  // namespace lbm

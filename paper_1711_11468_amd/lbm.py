@@ -1,0 +1,294 @@
+"""ctypes binding of the gfx950 library ``_lib/liblbm.so`` (C ABI in
+``include/lbm.h``).  Argument marshalling only: every step of the update
+runs in the HIP kernels of the library.  PyTorch provides the device
+buffers and the stream.
+
+The library must have been built (``python -m paper_1711_11468_amd.build``);
+loading fails loudly otherwise.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "liblbm.so")
+
+SOA, AOS = 0, 1
+DIRECT, LIST = 0, 1
+F64, F32_SHIFTED, F16_SHIFTED = 0, 1, 2
+FULLWAY, HALFWAY = 0, 1
+VERIFY_SLAB, VERIFY_DUCT, VERIFY_REFERENCE = 0, 1, 2
+OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, ENONFINITE, ENOTCONV = 0, -1, -2, -3, -4, -5, -6
+
+_LAYOUTS = {"soa": SOA, "aos": AOS}
+_ADDR = {"direct": DIRECT, "list": LIST}
+_STORAGE = {"f64": F64, "f32s": F32_SHIFTED, "f16s": F16_SHIFTED}
+_BOUNCE = {"fullway": FULLWAY, "halfway": HALFWAY}
+ELEM_BYTES = {F64: 8, F32_SHIFTED: 4, F16_SHIFTED: 2}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("layout", ctypes.c_int32), ("addressing", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("bounce", ctypes.c_int32),
+                ("f16_scale_log2", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("tau_plus", ctypes.c_double),
+                ("magic_lambda", ctypes.c_double), ("g", ctypes.c_double * 3)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_fluid", ctypes.c_int64),
+                ("n_sites", ctypes.c_int64), ("stride", ctypes.c_int64),
+                ("pdf_bytes", ctypes.c_int64), ("mask_bytes", ctypes.c_int64),
+                ("adj_bytes", ctypes.c_int64), ("fluid_index_bytes", ctypes.c_int64),
+                ("node_map_bytes", ctypes.c_int64), ("u_prev_bytes", ctypes.c_int64),
+                ("scratch_bytes", ctypes.c_int64), ("bytes_per_update", ctypes.c_double)]
+
+
+class Buffers(ctypes.Structure):
+    _fields_ = [("pdf_a", ctypes.c_void_p), ("pdf_b", ctypes.c_void_p),
+                ("mask", ctypes.c_void_p), ("adj", ctypes.c_void_p),
+                ("fluid_index", ctypes.c_void_p), ("node_map", ctypes.c_void_p),
+                ("u_prev", ctypes.c_void_p), ("scratch", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3),
+                ("u_max", ctypes.c_double), ("residual", ctypes.c_double),
+                ("nonfinite", ctypes.c_int64), ("step", ctypes.c_int64)]
+
+
+class VerifyResult(ctypes.Structure):
+    _fields_ = [("max_abs", ctypes.c_double), ("rel_l2", ctypes.c_double),
+                ("ref_max", ctypes.c_double), ("n_compared", ctypes.c_int64)]
+
+
+EXPORTED = ["lbm_plan", "lbm_init_geometry", "lbm_init_fields", "lbm_step", "lbm_macroscopic",
+            "lbm_verify", "lbm_export_pdfs", "lbm_import_pdfs", "lbm_get_sizes",
+            "lbm_step_count", "lbm_current_buffer", "lbm_destroy", "lbm_strerror",
+            "lbm_last_error", "lbm_membench"]
+
+_lib = None
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = "%s failed: %s (%d)" % (where, load().lbm_strerror(code).decode(), code)
+        detail = load().lbm_last_error().decode()
+        if detail:
+            msg += ": " + detail
+        super().__init__(msg)
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("HIP library %s is missing: build it with "
+                           "`python -m paper_1711_11468_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    lib.lbm_plan.argtypes = [P(Params), vp, P(Sizes)]
+    lib.lbm_init_geometry.argtypes = [P(vp), P(Params), vp, P(Buffers), vp]
+    lib.lbm_init_fields.argtypes = [vp, vp, vp]
+    lib.lbm_step.argtypes = [vp, ctypes.c_int32]
+    lib.lbm_macroscopic.argtypes = [vp, vp, vp, P(Stats)]
+    lib.lbm_verify.argtypes = [vp, ctypes.c_int32, vp, P(VerifyResult)]
+    lib.lbm_export_pdfs.argtypes = [vp, vp, ctypes.c_int64, vp]
+    lib.lbm_import_pdfs.argtypes = [vp, vp]
+    lib.lbm_get_sizes.argtypes = [vp, P(Sizes)]
+    lib.lbm_step_count.argtypes = [vp]
+    lib.lbm_step_count.restype = ctypes.c_int64
+    lib.lbm_current_buffer.argtypes = [vp]
+    lib.lbm_destroy.argtypes = [vp]
+    lib.lbm_destroy.restype = None
+    lib.lbm_strerror.argtypes = [ctypes.c_int]
+    lib.lbm_strerror.restype = ctypes.c_char_p
+    lib.lbm_last_error.argtypes = []
+    lib.lbm_last_error.restype = ctypes.c_char_p
+    lib.lbm_membench.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int64, ctypes.c_int64,
+                                 ctypes.c_int32, vp]
+    for name in ("lbm_plan", "lbm_init_geometry", "lbm_init_fields", "lbm_step",
+                 "lbm_macroscopic", "lbm_verify", "lbm_export_pdfs", "lbm_import_pdfs",
+                 "lbm_get_sizes", "lbm_current_buffer", "lbm_membench"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code, where):
+    if code != OK:
+        raise LBMError(code, where)
+
+
+def make_params(shape, tau_plus=0.8, magic=3.0 / 16.0, g=(0.0, 0.0, 0.0), layout="soa",
+                addressing="direct", storage="f64", bounce="fullway", f16_scale_log2=14,
+                block=0, pad=-1) -> Params:
+    nz, ny, nx = shape
+    p = Params()
+    p.nx, p.ny, p.nz = nx, ny, nz
+    p.layout = _LAYOUTS[layout]
+    p.addressing = _ADDR[addressing]
+    p.storage = _STORAGE[storage]
+    p.bounce = _BOUNCE[bounce]
+    p.f16_scale_log2 = f16_scale_log2
+    p.block = block
+    p.pad = pad
+    p.tau_plus = tau_plus
+    p.magic_lambda = magic
+    p.g[0], p.g[1], p.g[2] = (float(v) for v in g)
+    return p
+
+
+def plan(mask: np.ndarray, **kw) -> Sizes:
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    p = make_params(m.shape, **kw)
+    s = Sizes()
+    _check(load().lbm_plan(ctypes.byref(p), m.ctypes.data, ctypes.byref(s)), "lbm_plan")
+    return s
+
+
+class Lattice:
+    """A D3Q19 TRT lattice on one GPU.
+
+    ``mask``: uint8 array (nz, ny, nx), 1 = solid.  Keyword arguments are
+    those of :func:`make_params`.  Device buffers are torch tensors owned by
+    this object; the library borrows them.  Work runs on torch's current
+    stream of ``device`` at construction time.
+    """
+
+    def __init__(self, mask: np.ndarray, device=None, residual=True, **kw):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the lattice runs only on the HIP device")
+        lib = load()
+        self.torch = torch
+        self.mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        self.params = make_params(self.mask.shape, **kw)
+        self.kw = dict(kw)
+        self.sizes = Sizes()
+        _check(lib.lbm_plan(ctypes.byref(self.params), self.mask.ctypes.data,
+                            ctypes.byref(self.sizes)), "lbm_plan")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        s = self.sizes
+
+        def alloc(nbytes):
+            n = max(int(nbytes), 256)
+            return torch.empty(n, dtype=torch.uint8, device=self.device)
+
+        self._t = {
+            "pdf_a": alloc(s.pdf_bytes), "pdf_b": alloc(s.pdf_bytes),
+            "mask": alloc(s.mask_bytes), "scratch": alloc(s.scratch_bytes),
+        }
+        if self.params.addressing == LIST:
+            self._t["adj"] = alloc(s.adj_bytes)
+            self._t["fluid_index"] = alloc(s.fluid_index_bytes)
+            self._t["node_map"] = alloc(s.node_map_bytes)
+        if residual:
+            self._t["u_prev"] = alloc(s.u_prev_bytes)
+        b = Buffers()
+        for name, t in self._t.items():
+            setattr(b, name, t.data_ptr())
+        self.buffers = b
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.lbm_init_geometry(ctypes.byref(self.ctx), ctypes.byref(self.params),
+                                         self.mask.ctypes.data, ctypes.byref(b),
+                                         ctypes.c_void_p(self.stream.cuda_stream)),
+                   "lbm_init_geometry")
+
+    # -- properties ---------------------------------------------------------
+    @property
+    def n_nodes(self):
+        return self.sizes.n_nodes
+
+    @property
+    def n_fluid(self):
+        return self.sizes.n_fluid
+
+    @property
+    def step_count(self):
+        return load().lbm_step_count(self.ctx)
+
+    def current_buffer_tensor(self):
+        return self._t["pdf_a"] if load().lbm_current_buffer(self.ctx) == 0 else self._t["pdf_b"]
+
+    # -- operations ---------------------------------------------------------
+    def step(self, n: int = 1):
+        _check(load().lbm_step(self.ctx, int(n)), "lbm_step")
+
+    def macroscopic(self, fields: bool = False, allow_nonfinite: bool = False):
+        torch = self.torch
+        rho = u = None
+        if fields:
+            rho = torch.empty(self.n_nodes, dtype=torch.float64, device=self.device)
+            u = torch.empty(3 * self.n_nodes, dtype=torch.float64, device=self.device)
+        st = Stats()
+        rc = load().lbm_macroscopic(self.ctx, rho.data_ptr() if fields else None,
+                                    u.data_ptr() if fields else None, ctypes.byref(st))
+        if not (allow_nonfinite and rc == ENONFINITE):
+            _check(rc, "lbm_macroscopic")
+        out = {"mass": st.mass, "momentum": list(st.momentum), "u_max": st.u_max,
+               "residual": st.residual, "nonfinite": st.nonfinite, "step": st.step, "rc": rc}
+        if fields:
+            out["rho"] = rho
+            out["u"] = u.view(3, self.n_nodes)
+        return out
+
+    def verify(self, kind: int, ref=None):
+        r = VerifyResult()
+        _check(load().lbm_verify(self.ctx, int(kind), None if ref is None else ref.data_ptr(),
+                                 ctypes.byref(r)), "lbm_verify")
+        return {"max_abs": r.max_abs, "rel_l2": r.rel_l2, "ref_max": r.ref_max,
+                "n_compared": r.n_compared}
+
+    def export(self, nodes=None) -> np.ndarray:
+        """Canonical pre-collision populations [count][19] float64."""
+        if nodes is None:
+            out = np.empty((self.n_nodes, 19), dtype=np.float64)
+            _check(load().lbm_export_pdfs(self.ctx, None, self.n_nodes, out.ctypes.data),
+                   "lbm_export_pdfs")
+            return out
+        ids = np.ascontiguousarray(nodes, dtype=np.int64).reshape(-1)
+        out = np.empty((ids.size, 19), dtype=np.float64)
+        _check(load().lbm_export_pdfs(self.ctx, ids.ctypes.data, ids.size, out.ctypes.data),
+               "lbm_export_pdfs")
+        return out
+
+    def import_(self, f: np.ndarray):
+        a = np.ascontiguousarray(f, dtype=np.float64).reshape(self.n_nodes, 19)
+        _check(load().lbm_import_pdfs(self.ctx, a.ctypes.data), "lbm_import_pdfs")
+
+    def init_fields(self, rho=None, u=None):
+        """Equilibrium start from device float64 tensors rho[N] and u[3][N]."""
+        _check(load().lbm_init_fields(self.ctx, None if rho is None else rho.data_ptr(),
+                                      None if u is None else u.data_ptr()), "lbm_init_fields")
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            load().lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def membench(kind: int, a, b, n: int, stride: int, block: int = 256, stream=None):
+    """Launch one memory micro-benchmark kernel (see include/lbm.h)."""
+    s = stream if stream is not None else 0
+    _check(load().lbm_membench(int(kind), None if a is None else a.data_ptr(), b.data_ptr(),
+                               int(n), int(stride), int(block), ctypes.c_void_p(s)),
+           "lbm_membench")

@@ -1,0 +1,99 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and its host-only planning and validation behave as
+documented.  No GPU work is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1711_11468_amd import inputs as I
+from paper_1711_11468_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lbm.load()
+    declared = _declared()
+    assert {"lbm_plan", "lbm_init_geometry", "lbm_step", "lbm_macroscopic", "lbm_verify"} <= declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(lbm.EXPORTED) == declared
+
+
+def test_plan_sizes_channel():
+    m = I.channel_mask(64, 32, 32)
+    s = lbm.plan(m)
+    assert s.n_nodes == 64 * 32 * 32 and s.n_fluid == 64 * 30 * 30 and s.n_sites == s.n_nodes
+    assert s.stride >= s.n_nodes and (s.stride * 8) % 256 == 0
+    assert s.pdf_bytes == s.stride * 19 * 8
+    assert s.bytes_per_update == 305.0  # 19 loads + 19 stores of 8 B + 1 flag byte
+    s = lbm.plan(m, layout="aos")
+    assert s.stride == 19 and s.pdf_bytes >= 64 * 32 * 32 * 152
+    s = lbm.plan(m, addressing="list", bounce="halfway")
+    assert s.n_sites == s.n_fluid and s.adj_bytes >= 18 * 4 * s.n_fluid
+    assert s.bytes_per_update == 376.0
+    s = lbm.plan(m, storage="f32s")
+    assert s.bytes_per_update == 153.0
+    s = lbm.plan(m, storage="f16s")
+    assert s.bytes_per_update == 77.0
+
+
+def test_byte_model_matches_table1():
+    """The library's byte model reproduces the paper's Table 1 loop balances:
+    the list pull with non-temporal stores is 376 B/FLUP; adding the
+    write-allocate read of the destination (the CPU kernels without
+    non-temporal stores) gives 456 (full array) and 528 (list)."""
+    rows = {}
+    with open(os.path.join(HERE, "golden", "loop_balance_table1.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                rows[k] = float(v)
+    m = np.zeros((4, 4, 4), dtype=np.uint8)
+    direct = lbm.plan(m).bytes_per_update - 1.0  # without the flag byte
+    lst = lbm.plan(m, addressing="list", bounce="halfway").bytes_per_update
+    write_allocate = 19 * 8
+    assert lst == rows["os-list-nt"]
+    assert direct + write_allocate == rows["os-full-array"]
+    assert lst + write_allocate == rows["os-list"]
+
+
+@pytest.mark.parametrize("kw", [dict(tau_plus=0.5), dict(magic=0.0), dict(layout="aos", addressing="list", bounce="halfway"),
+                                dict(addressing="list", bounce="fullway"), dict(block=96),
+                                dict(storage="f16s", f16_scale_log2=30), dict(pad=-2)])
+def test_plan_rejects_bad_parameters(kw):
+    m = np.zeros((4, 4, 4), dtype=np.uint8)
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.plan(m, **kw)
+    assert e.value.code == lbm.EINVAL
+
+
+def test_plan_overflow():
+    lib = lbm.load()
+    p = lbm.make_params((2048, 1024, 1024))
+    s = lbm.Sizes()
+    tiny = np.zeros(1, dtype=np.uint8)  # not read: the size check comes first
+    assert lib.lbm_plan(ctypes.byref(p), tiny.ctypes.data, ctypes.byref(s)) == lbm.EOVERFLOW
+    assert b"32-bit" in lib.lbm_last_error() or b"too large" in lib.lbm_last_error()
+
+
+def test_null_arguments_rejected():
+    lib = lbm.load()
+    assert lib.lbm_step(None, 1) == lbm.EINVAL
+    assert lib.lbm_plan(None, None, None) == lbm.EINVAL
+    assert lib.lbm_step_count(None) == -1
+    assert lib.lbm_strerror(lbm.ENONFINITE) == b"non-finite populations"

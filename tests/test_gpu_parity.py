@@ -1,0 +1,214 @@
+"""GPU parity: the HIP sweeps against the CPU oracle, element by element.
+
+All comparisons use the canonical pre-collision populations exported by the
+library.  FP64 paths must agree with the oracle within 1e-12 relative
+max-abs (max |f_gpu - f_oracle| / max |f_oracle|).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1711_11468_amd import inputs as I
+from tests._util import BOUNCE, oracle_window_sample, random_state, rel_maxabs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1711_11468_amd import lbm
+    lbm.load()
+    return lbm
+
+
+def _case(mask, steps, L, f0=None, **kw):
+    phys = dict(tau_plus=kw.pop("tau_plus", 0.8), magic=kw.pop("magic", 3 / 16),
+                g=kw.pop("g", (1e-6, 0.0, 0.0)))
+    bounce = kw.get("bounce", "fullway")
+    lat = L.Lattice(mask, **phys, **kw)
+    if f0 is not None:
+        lat.import_(f0)
+    lat.step(steps)
+    got = lat.export()
+    start = f0 if f0 is not None else O.rest_state(mask, BOUNCE[bounce])
+    ref = O.run(mask, start, steps, phys["tau_plus"], phys["magic"], phys["g"], BOUNCE[bounce])
+    return got, ref, lat
+
+
+def test_channel_64x32x32_200_steps_soa(L):
+    """Plain D3Q19 TRT fp64 on the 64x32x32 channel (x periodic, full-way
+    walls), g_x = 1e-6, tau+ = 0.8, Lambda = 3/16, rest start, 200 steps."""
+    mask = I.channel_mask(64, 32, 32)
+    got, ref, lat = _case(mask, 200, L)
+    print("parity rel max-abs", rel_maxabs(got, ref))
+    assert rel_maxabs(got, ref) <= TOL
+    _, w, _ = O.table()
+    h_err = np.abs(got - ref).max() / np.abs(ref - w).max()
+    assert h_err <= 1e-9  # the flow part of the populations (f - w) agrees too
+    assert np.abs(ref - w).max() > 1e-6  # the flow has actually developed
+
+
+@pytest.mark.parametrize("layout,bounce", [("soa", "fullway"), ("soa", "halfway"),
+                                           ("aos", "fullway"), ("aos", "halfway")])
+@pytest.mark.parametrize("shape", [(9, 10, 12), (5, 7, 131)])
+def test_direct_random_state(L, layout, bounce, shape):
+    """Random solids (~20 %), random populations and a 3-component force:
+    any index or sign error shows.  (5, 7, 131): rows longer than one
+    workgroup pass with a ragged tail."""
+    nz, ny, nx = shape
+    mask = I.random_solid_mask(nx, ny, nz, seed=3, fraction=0.2)
+    f0 = random_state(mask, seed=9, amplitude=0.02, bounce=bounce)
+    got, ref, _ = _case(mask, 25, L, f0=f0, layout=layout, bounce=bounce, block=64,
+                        g=(1e-4, -2e-5, 3e-5), tau_plus=0.7, magic=1 / 4)
+    assert rel_maxabs(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("shape", [(9, 10, 12), (6, 9, 70)])
+def test_list_random_state(L, shape):
+    nz, ny, nx = shape
+    mask = I.random_solid_mask(nx, ny, nz, seed=5, fraction=0.3)
+    f0 = random_state(mask, seed=4, amplitude=0.02, bounce="halfway")
+    got, ref, lat = _case(mask, 25, L, f0=f0, addressing="list", bounce="halfway",
+                          g=(-3e-5, 1e-4, 2e-5), tau_plus=1.1, magic=1 / 12)
+    assert lat.n_fluid == int((mask == 0).sum())
+    assert rel_maxabs(got, ref) <= TOL
+
+
+def test_spheres_list_and_direct(L):
+    """Porous box of overlapping spheres, fully periodic, both addressings."""
+    mask, phi, _ = I.spheres_mask(40, 36, 32, seed=1, porosity=0.5, rmin=3, rmax=6)
+    for kw in ({"addressing": "list", "bounce": "halfway"},
+               {"addressing": "direct", "bounce": "halfway"},
+               {"addressing": "direct", "bounce": "fullway"}):
+        got, ref, _ = _case(mask, 40, L, **kw)
+        assert rel_maxabs(got, ref) <= TOL, kw
+
+
+def test_import_export_roundtrip(L):
+    """Import followed by export returns the canonical state bit for bit."""
+    mask = I.random_solid_mask(11, 7, 6, seed=8, fraction=0.25)
+    for kw in ({"layout": "soa", "bounce": "fullway"}, {"layout": "aos", "bounce": "halfway"},
+               {"addressing": "list", "bounce": "halfway"}):
+        f0 = random_state(mask, seed=1, amplitude=0.05, bounce=kw["bounce"])
+        lat = L.Lattice(mask, **kw)
+        lat.import_(f0)
+        assert np.array_equal(lat.export(), f0), kw
+
+
+def test_block_size_bitwise_and_layouts_agree(L):
+    """Results do not depend on the workgroup size (bitwise: no races, no
+    order dependence) and SoA, AoS and list (all half-way) agree to
+    round-off (the compiler may contract multiply-adds differently)."""
+    mask = I.random_solid_mask(150, 6, 5, seed=2, fraction=0.15)
+    f0 = random_state(mask, seed=3, amplitude=0.02, bounce="halfway")
+
+    def run(**kw):
+        lat = L.Lattice(mask, bounce="halfway", g=(1e-5, 0, 0), **kw)
+        lat.import_(f0)
+        lat.step(12)
+        return lat.export()
+
+    for base, blocks in (({}, (64, 128, 256, 1024)), ({"layout": "aos"}, (64, 256, 512)),
+                         ({"addressing": "list"}, (64, 256, 1024))):
+        outs = [run(block=b, **base) for b in blocks]
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0]), base
+    ref = run()
+    for kw in ({"layout": "aos"}, {"addressing": "list"}):
+        assert rel_maxabs(run(**kw), ref) <= 1e-15, kw
+
+
+def test_full_size_channel_512_sampled(L):
+    """512^3 channel in the benchmark's launch configuration: sampled nodes
+    (corners, walls, interior) against the windowed oracle after 12 steps,
+    and every x-slice identical (x-invariance of the duct flow)."""
+    n, steps = 512, 12
+    mask = I.channel_mask(n, n, n)
+    phys = dict(tau_plus=0.8, magic=3 / 16, g=(1e-6, 0.0, 0.0))
+    lat = L.Lattice(mask, **phys)
+    lat.step(steps)
+    pts = [(0, 1, 1), (5, 1, 2), (511, 2, 1), (100, 255, 256), (7, 510, 510), (300, 1, 300),
+           (0, 0, 0), (400, 511, 17)]
+    ids = [x + n * (y + n * z) for x, y, z in pts]
+    got = lat.export(ids)
+    for k, c in enumerate(pts):
+        ref = oracle_window_sample(mask, c, steps, **phys)
+        assert rel_maxabs(got[k], ref) <= TOL, c
+    # x-invariance on one cross-section line
+    row = [x + n * (3 + n * 2) for x in range(0, n, 37)]
+    vals = lat.export(row)
+    assert np.array_equal(vals, np.repeat(vals[:1], len(row), axis=0))
+    st = lat.macroscopic()
+    # mass over all nodes (walls hold populations in transit) is conserved
+    assert abs(st["mass"] - n ** 3) <= 1e-12 * n ** 3
+
+
+def test_full_size_spheres_384_list_sampled(L):
+    """384^3 porous box (list addressing) against the windowed oracle."""
+    n, steps = 384, 8
+    mask, phi, _ = I.spheres_mask(n, n, n, seed=0, porosity=0.4, rmin=8, rmax=16)
+    phys = dict(tau_plus=0.8, magic=3 / 16, g=(1e-6, 0.0, 0.0))
+    lat = L.Lattice(mask, addressing="list", bounce="halfway", **phys)
+    lat.step(steps)
+    rng = np.random.default_rng(7)
+    fluid = np.flatnonzero(mask.reshape(-1) == 0)
+    ids = rng.choice(fluid, 12, replace=False)
+    got = lat.export(ids)
+    for k, lin in enumerate(ids):
+        c = (int(lin % n), int((lin // n) % n), int(lin // (n * n)))
+        ref = oracle_window_sample(mask, c, steps, bounce="halfway", **phys)
+        assert rel_maxabs(got[k], ref) <= TOL, c
+
+
+def test_diagnostics_mass_momentum(L):
+    """Mass is conserved and momentum grows by Nf g per step (no solids)."""
+    mask = np.zeros((6, 7, 9), dtype=np.uint8)
+    g = np.array([1e-4, -2e-5, 5e-5])
+    f0 = random_state(mask, seed=6, amplitude=0.02, bounce="fullway")
+    lat = L.Lattice(mask, g=tuple(g))
+    lat.import_(f0)
+    s0 = lat.macroscopic()
+    lat.step(7)
+    s1 = lat.macroscopic()
+    assert abs(s1["mass"] - s0["mass"]) <= 1e-13 * s0["mass"]
+    np.testing.assert_allclose(np.array(s1["momentum"]) - np.array(s0["momentum"]),
+                               7 * mask.size * g, atol=1e-13)
+    # fields agree with the oracle's macroscopic quantities
+    ref = O.run(mask, f0, 7, 0.8, 3 / 16, g, 0)
+    rho_o, u_o = O.macroscopic(mask, ref, g)
+    s2 = lat.macroscopic(fields=True)
+    np.testing.assert_allclose(s2["rho"].cpu().numpy(), rho_o, rtol=1e-13)
+    np.testing.assert_allclose(s2["u"].cpu().numpy().T, u_o, atol=1e-15)
+
+
+def test_residual_and_slab_verify(L):
+    """Run the slab to steady state with the residual driver and verify the
+    parabola (Lambda = 3/16 makes it exact)."""
+    mask = I.slab_mask(4, 4, 12)
+    lat = L.Lattice(mask, g=(1e-5, 0, 0), bounce="halfway")
+    lat.macroscopic()
+    r = 1.0
+    for _ in range(200):
+        lat.step(100)
+        r = lat.macroscopic()["residual"]
+        if r < 1e-12:
+            break
+    assert r < 1e-12
+    v = lat.verify(L.VERIFY_SLAB)
+    assert v["rel_l2"] < 1e-10
+    assert v["n_compared"] == 4 * 4 * 10
+
+
+def test_nonfinite_detected(L):
+    mask = I.channel_mask(8, 6, 6)
+    lat = L.Lattice(mask)
+    f = O.rest_state(mask, 0)
+    f[2 + 8 * (2 + 6 * 2), 3] = np.nan
+    lat.import_(f)
+    st = lat.macroscopic(allow_nonfinite=True)
+    assert st["rc"] == L.ENONFINITE and st["nonfinite"] >= 1
