@@ -75,7 +75,12 @@ extern "C" {
 
 #define LBM_F64 0            /* double populations (the paper's storage)   */
 #define LBM_F32_SHIFTED 1    /* float  h = f - w, float collide            */
-#define LBM_F16_SHIFTED 2    /* _Float16 h = (f - w) * 2^s, float collide  */
+#define LBM_F16_SHIFTED 2    /* _Float16 h = (f - w) * 2^s, float collide,
+                                round to nearest even on store             */
+#define LBM_F16_SHIFTED_SR 3 /* as LBM_F16_SHIFTED, stochastic rounding on
+                                store (hash of node, direction, step): the
+                                expected stored value is exact, so updates
+                                smaller than half an ulp are not lost      */
 
 #define LBM_FULLWAY 0        /* solids store and reverse populations       */
 #define LBM_HALFWAY 1        /* mid-link reflection in the same step       */
@@ -89,13 +94,17 @@ typedef struct {
   int32_t nx, ny, nz;       /* nodes per axis, walls included; each >= 1   */
   int32_t layout;           /* LBM_SOA | LBM_AOS (LBM_LIST requires SOA)   */
   int32_t addressing;       /* LBM_DIRECT | LBM_LIST                       */
-  int32_t storage;          /* LBM_F64 | LBM_F32_SHIFTED | LBM_F16_SHIFTED */
+  int32_t storage;          /* LBM_F64 | LBM_F32_SHIFTED | LBM_F16_SHIFTED
+                               | LBM_F16_SHIFTED_SR                        */
   int32_t bounce;           /* LBM_FULLWAY | LBM_HALFWAY (LIST: HALFWAY)   */
-  int32_t f16_scale_log2;   /* s for LBM_F16_SHIFTED, 0..24; else ignored  */
+  int32_t f16_scale_log2;   /* s for the F16 storages, 0..24; else ignored */
   int32_t block;            /* threads per workgroup, 0 = default; a
                                multiple of 64 up to 1024                   */
   int32_t pad;              /* extra elements between direction arrays
                                (SOA/LIST); -1 = automatic                  */
+  int32_t cu_slots;         /* at most this many sweep workgroups per
+                               compute unit (reserved LDS caps residency);
+                               0 = no cap                                  */
   double tau_plus;          /* > 1/2; kinematic viscosity (tau+ - 1/2)/3   */
   double magic_lambda;      /* Lambda > 0                                  */
   double g[3];              /* body-force density, lattice units           */
@@ -112,6 +121,7 @@ typedef struct {
   int64_t adj_bytes;        /* LIST: 18*stride int32; else 0               */
   int64_t fluid_index_bytes;/* LIST: Nf int32 (list -> node); else 0       */
   int64_t node_map_bytes;   /* LIST: N int32 (node -> list or -1); else 0  */
+  int64_t links_bytes;      /* DIRECT + HALFWAY: N uint32 link words       */
   int64_t u_prev_bytes;     /* 3*n_sites doubles for the residual          */
   int64_t scratch_bytes;    /* reduction partials                          */
   double bytes_per_update;  /* algorithmic HBM bytes per site update       */
@@ -124,6 +134,8 @@ typedef struct {            /* device pointers, caller-owned               */
   int32_t* adj;             /* LIST only, else NULL                        */
   int32_t* fluid_index;     /* LIST only, else NULL                        */
   int32_t* node_map;        /* LIST only, else NULL                        */
+  uint32_t* links;          /* DIRECT + HALFWAY only (bit 0: node solid,
+                               bit i: neighbour x - c_i solid), else NULL  */
   double* u_prev;           /* optional (NULL: no residual)                */
   void* scratch;            /* scratch_bytes                               */
 } lbm_buffers;
@@ -159,7 +171,8 @@ typedef struct lbm_ctx lbm_ctx;
 int lbm_plan(const lbm_params* params, const uint8_t* mask_host, lbm_sizes* out);
 
 /* Geometry set-up (Sect. 3 "Lattice Representation"; Sect. 3.2): copies the
- * mask to bufs->mask; for LIST builds the fluid-node vector (x fastest),
+ * mask to bufs->mask; for DIRECT + HALFWAY builds the link words; for LIST
+ * builds the fluid-node vector (x fastest),
  * the node map and the adjacency list (18 int32 per node: the slot a pull
  * reads for direction i, which is the neighbour's slot, wrapped
  * periodically, or the node's own opposite slot when the neighbour is solid

@@ -39,31 +39,77 @@ __host__ __device__ constexpr double weight(int i) {
 // R: arithmetic type of the collision; T: element type in memory.
 // Shifted formats store h_i = f_i - w_i (scaled by 2^s for half precision)
 // and run the collision on h directly.
+// store(v, scale, key): key identifies (node, direction, time step) and is
+// used only by the stochastically rounded format.
 struct StoreF64 {
   using T = double;
   using R = double;
   static constexpr bool kShifted = false;
+  static constexpr bool kStochastic = false;
   __device__ __forceinline__ static R load(T v, R) { return v; }
-  __device__ __forceinline__ static T store(R v, R) { return v; }
+  __device__ __forceinline__ static T store(R v, R, uint32_t) { return v; }
 };
 
 struct StoreF32Shifted {
   using T = float;
   using R = float;
   static constexpr bool kShifted = true;
+  static constexpr bool kStochastic = false;
   __device__ __forceinline__ static R load(T v, R) { return v; }
-  __device__ __forceinline__ static T store(R v, R) { return v; }
+  __device__ __forceinline__ static T store(R v, R, uint32_t) { return v; }
 };
 
 struct StoreF16Shifted {
   using T = _Float16;
   using R = float;
   static constexpr bool kShifted = true;
+  static constexpr bool kStochastic = false;
   // scale = 2^s on store, 2^-s on load: exact (power of two), so the only
   // rounding is the float -> half conversion (round to nearest even).
   __device__ __forceinline__ static R load(T v, R inv_scale) { return (R)v * inv_scale; }
-  __device__ __forceinline__ static T store(R v, R scale) { return (T)(v * scale); }
+  __device__ __forceinline__ static T store(R v, R scale, uint32_t) { return (T)(v * scale); }
 };
+
+// 32-bit finaliser of MurmurHash3 (Appleby): a bijective avalanche mixer.
+__device__ __forceinline__ uint32_t mix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// float -> half with stochastic rounding: add 13 random bits below the last
+// half-precision mantissa bit of the magnitude, then truncate; the result is
+// exactly representable, so the conversion itself is exact.  Rounds up with
+// probability equal to the fraction of the ulp, so the expected stored value
+// equals the input (small increments are not lost).  Values outside the
+// normal half range fall back to round-to-nearest-even.
+__device__ __forceinline__ _Float16 f32_to_f16_stochastic(float v, uint32_t rnd) {
+  const uint32_t b = __float_as_uint(v);
+  uint32_t mag = b & 0x7fffffffu;
+  if (mag < 0x38800000u || mag >= 0x477fe000u) return (_Float16)v;
+  mag = (mag + (rnd & 0x1fffu)) & ~0x1fffu;
+  if (mag > 0x477fe000u) mag = 0x477fe000u;
+  return (_Float16)__uint_as_float((b & 0x80000000u) | mag);
+}
+
+struct StoreF16ShiftedSR {
+  using T = _Float16;
+  using R = float;
+  static constexpr bool kShifted = true;
+  static constexpr bool kStochastic = true;
+  __device__ __forceinline__ static R load(T v, R inv_scale) { return (R)v * inv_scale; }
+  __device__ __forceinline__ static T store(R v, R scale, uint32_t key) {
+    return f32_to_f16_stochastic(v * scale, mix32(key));
+  }
+};
+
+// Random key of the value stored for (node n, direction i) at time step t.
+__device__ __forceinline__ uint32_t sr_key(uint32_t n, int i, uint32_t t) {
+  return mix32(n * 0x9E3779B1u + (uint32_t)i) ^ (t * 0x85ebca77u + 0x165667b1u);
+}
 
 // Collision constants in the arithmetic type.
 template <typename R>
@@ -72,6 +118,7 @@ struct Collide {
   R ap, am;          // 1 - 1/(2 tau+), 1 - 1/(2 tau-)
   R gx, gy, gz;      // body-force density
   R scale, inv_scale;  // storage scale (half precision only), else 1
+  uint32_t step;       // time step being computed (stochastic rounding key)
 };
 
 // In-place TRT collision of one fluid node.  SHIFTED: f holds h = f - w.

@@ -151,7 +151,8 @@ hipError_t dispatch(const lbm_params& p, F&& f) {
   switch (p.storage) {
     case LBM_F64: return by_store(StoreF64{});
     case LBM_F32_SHIFTED: return by_store(StoreF32Shifted{});
-    default: return by_store(StoreF16Shifted{});
+    case LBM_F16_SHIFTED: return by_store(StoreF16Shifted{});
+    default: return by_store(StoreF16ShiftedSR{});
   }
 }
 

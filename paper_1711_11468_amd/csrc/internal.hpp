@@ -29,6 +29,7 @@ inline void* pdf_buf(lbm_ctx* c, int which) { return which == 0 ? c->b.pdf_a : c
 hipError_t launch_sweep(lbm_ctx* c, const void* src, void* dst);
 hipError_t launch_fill_rest(lbm_ctx* c, void* buf);
 hipError_t launch_build_adjacency(lbm_ctx* c);
+hipError_t launch_build_links(lbm_ctx* c);
 hipError_t launch_export(lbm_ctx* c, const void* src, const int64_t* ids_dev, int64_t count,
                          double* out_dev);
 hipError_t launch_import(lbm_ctx* c, const double* canon_dev, void* dst);

@@ -35,7 +35,7 @@ static int hip_fail(hipError_t e, const char* what) {
   } while (0)
 
 static int elem_size(int storage) {
-  return storage == LBM_F64 ? 8 : (storage == LBM_F32_SHIFTED ? 4 : 2);
+  return storage == LBM_F64 ? 8 : (storage == LBM_F32_SHIFTED ? 4 : 2);  // F16 kinds: 2
 }
 
 static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
@@ -48,13 +48,14 @@ static int validate(const lbm_params* p) {
   if (!(p->magic_lambda > 0.0)) { set_error("magic_lambda must be positive"); return LBM_EINVAL; }
   if (p->layout != LBM_SOA && p->layout != LBM_AOS) { set_error("bad layout"); return LBM_EINVAL; }
   if (p->addressing != LBM_DIRECT && p->addressing != LBM_LIST) { set_error("bad addressing"); return LBM_EINVAL; }
-  if (p->storage < LBM_F64 || p->storage > LBM_F16_SHIFTED) { set_error("bad storage"); return LBM_EINVAL; }
+  if (p->storage < LBM_F64 || p->storage > LBM_F16_SHIFTED_SR) { set_error("bad storage"); return LBM_EINVAL; }
   if (p->bounce != LBM_FULLWAY && p->bounce != LBM_HALFWAY) { set_error("bad bounce"); return LBM_EINVAL; }
   if (p->addressing == LBM_LIST && (p->layout != LBM_SOA || p->bounce != LBM_HALFWAY)) {
     set_error("list addressing requires SOA layout and half-way bounce-back");
     return LBM_EINVAL;
   }
-  if (p->storage == LBM_F16_SHIFTED && (p->f16_scale_log2 < 0 || p->f16_scale_log2 > 24)) {
+  if ((p->storage == LBM_F16_SHIFTED || p->storage == LBM_F16_SHIFTED_SR) &&
+      (p->f16_scale_log2 < 0 || p->f16_scale_log2 > 24)) {
     set_error("f16_scale_log2 must be in [0, 24]");
     return LBM_EINVAL;
   }
@@ -63,6 +64,7 @@ static int validate(const lbm_params* p) {
     return LBM_EINVAL;
   }
   if (p->pad < -1 || p->pad > (1 << 24)) { set_error("pad must be -1 or in [0, 2^24]"); return LBM_EINVAL; }
+  if (p->cu_slots < 0 || p->cu_slots > 64) { set_error("cu_slots must be in [0, 64]"); return LBM_EINVAL; }
   for (int a = 0; a < 3; ++a)
     if (!(p->g[a] == p->g[a]) || p->g[a] > 1e30 || p->g[a] < -1e30) { set_error("bad g"); return LBM_EINVAL; }
   return LBM_OK;
@@ -101,11 +103,15 @@ static int plan_sizes(const lbm_params* p, int64_t n_fluid, lbm_sizes* s) {
     s->fluid_index_bytes = round_up((n_fluid < 1 ? 1 : n_fluid) * 4, 256);
     s->node_map_bytes = round_up(N * 4, 256);
   }
+  const bool links = p->addressing == LBM_DIRECT && p->bounce == LBM_HALFWAY;
+  if (links) s->links_bytes = round_up(N * 4, 256);
   s->u_prev_bytes = round_up(3 * (s->n_sites < 1 ? 1 : s->n_sites) * 8, 256);
   s->scratch_bytes = round_up((int64_t)(4096 + 1) * kStatSlots * 8, 256);
   // Algorithmic HBM bytes per site update: 19 loads + 19 stores of one
-  // element, plus the flag byte (direct) or 18 int32 adjacency entries (list).
-  s->bytes_per_update = 2.0 * Q * es + (p->addressing == LBM_LIST ? 4.0 * (Q - 1) : 1.0);
+  // element, plus the flag byte (direct, full-way), the link word (direct,
+  // half-way) or 18 int32 adjacency entries (list).
+  s->bytes_per_update =
+      2.0 * Q * es + (p->addressing == LBM_LIST ? 4.0 * (Q - 1) : (links ? 4.0 : 1.0));
   return LBM_OK;
 }
 
@@ -172,6 +178,10 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
     set_error("list addressing needs adj, fluid_index and node_map");
     return LBM_EINVAL;
   }
+  if (s.links_bytes > 0 && !bufs->links) {
+    set_error("direct addressing with half-way bounce-back needs the links buffer");
+    return LBM_EINVAL;
+  }
   lbm_ctx* c = new (std::nothrow) lbm_ctx();
   if (!c) { set_error("host allocation failed"); return LBM_ENOMEM; }
   c->p = *params;
@@ -182,11 +192,14 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
     c->b.fluid_index = nullptr;
     c->b.node_map = nullptr;
   }
+  if (s.links_bytes == 0) c->b.links = nullptr;
   c->stream = (hipStream_t)stream;
   c->cur = 0;
   c->step = 0;
   c->u_prev_valid = 0;
-  c->block = params->block ? params->block : 256;
+  // 512 threads: one workgroup covers a 512-node row in one pass, which
+  // measured fastest for the direct sweeps; the list sweep likes it too.
+  c->block = params->block ? params->block : 512;
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) { delete c; return hip_fail(e, "hipGetDevice"); }
 
@@ -196,6 +209,10 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
   };
   e = hipMemcpyAsync(c->b.mask, mask_host, (size_t)N, hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return fail(e, "mask upload");
+  if (c->b.links) {
+    e = launch_build_links(c);
+    if (e != hipSuccess) return fail(e, "link words kernel");
+  }
   if (params->addressing == LBM_LIST) {
     // Fluid-node vector in x-fastest order and the node -> list map.
     std::vector<int32_t> fidx, nmap;

@@ -16,7 +16,7 @@ static View make_view(const lbm_ctx* c) {
   v.adj = c->b.adj;
   v.node_map = c->b.node_map;
   v.fluid_index = c->b.fluid_index;
-  if (c->p.storage == LBM_F16_SHIFTED) {
+  if (c->p.storage == LBM_F16_SHIFTED || c->p.storage == LBM_F16_SHIFTED_SR) {
     v.scale = ldexpf(1.0f, c->p.f16_scale_log2);
     v.inv_scale = ldexpf(1.0f, -c->p.f16_scale_log2);
   } else {

@@ -3,13 +3,21 @@
 // Kernels with Non-Temporal Stores").  One launch advances the whole lattice
 // by one time step from the source buffer into the destination buffer.
 //
-// Direct addressing (full array + flag field): one workgroup per (y, z) row,
-// threads stride along x, so the +-x neighbour loads of a row stay inside
-// one workgroup (shared L1/L2 lines) and every load and store of a wavefront
-// is a contiguous run (SoA).  Periodic wrap is index arithmetic
+// Direct addressing, SoA (full array + flag field): one workgroup per (y, z)
+// row, threads stride along x, so the +-x neighbour loads of a row stay
+// inside one workgroup (shared L1/L2 lines) and every load and store of a
+// wavefront is a contiguous run.  Periodic wrap is index arithmetic
 // (Sect. 3.2); full-way bounce-back is the solid-node branch of the same
-// launch (solid nodes send back what they received), half-way bounce-back
-// replaces a pull from a solid neighbour by the node's own opposite slot.
+// launch (solid nodes send back what they received); half-way bounce-back
+// replaces a pull from a solid neighbour by the node's own opposite slot,
+// steered by a per-node 32-bit link word built once at set-up.
+//
+// Direct addressing, AoS: node records of 19 values are contiguous, so a
+// wavefront reading one direction of 64 nodes would touch 64 records.  The
+// workgroup instead stages each of the 9 source rows of its row segment
+// (the rows y - c_y, z - c_z the pull reads from) into LDS with contiguous
+// loads, picks the directions that row supplies, and writes its results
+// back through LDS as one contiguous run of records.
 //
 // List addressing (fluid-node vector + adjacency, Sect. 3): one thread per
 // fluid node; 18 int32 adjacency entries give the slot to pull for each
@@ -20,16 +28,13 @@
 
 namespace lbm {
 
-template <int LAYOUT>
-__device__ __forceinline__ int64_t slot(int64_t n, int i, int64_t stride) {
-  return LAYOUT == LBM_SOA ? (int64_t)i * stride + n : n * Q + i;
-}
+constexpr int kLdsPerCU = 163840;  // gfx950: 160 KiB of LDS per compute unit
 
-template <class ST, int LAYOUT, int BB>
+template <class ST, int BB>
 __global__ void __launch_bounds__(1024)
-k_sweep_direct(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
-               const uint8_t* __restrict__ mask, int nx, int ny, int nz, int64_t stride,
-               Collide<typename ST::R> k) {
+k_sweep_soa(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
+            const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx,
+            int ny, int nz, int64_t stride, Collide<typename ST::R> k) {
   using R = typename ST::R;
   const int row = blockIdx.x;
   const int y = row % ny;
@@ -39,7 +44,14 @@ k_sweep_direct(const typename ST::T* __restrict__ src, typename ST::T* __restric
   for (int x = threadIdx.x; x < nx; x += blockDim.x) {
     const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     const int n = x + nx * row;
-    const bool solid = mask[n] != 0;
+    uint32_t lk = 0;
+    bool solid;
+    if (BB == LBM_HALFWAY) {
+      lk = links[n];
+      solid = (lk & 1u) != 0;
+    } else {
+      solid = mask[n] != 0;
+    }
     R f[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -47,26 +59,113 @@ k_sweep_direct(const typename ST::T* __restrict__ src, typename ST::T* __restric
       const int sx = Vel::cx[i] == 1 ? xm : (Vel::cx[i] == -1 ? xp : x);
       const int sy = Vel::cy[i] == 1 ? ym : (Vel::cy[i] == -1 ? yp : y);
       const int sz = Vel::cz[i] == 1 ? zm : (Vel::cz[i] == -1 ? zp : z);
-      const int sn = sx + nx * (sy + ny * sz);
-      int64_t at = slot<LAYOUT>(sn, i, stride);
-      if (BB == LBM_HALFWAY && i != 0) {
-        if (!solid && mask[sn] != 0) at = slot<LAYOUT>(n, Vel::opp[i], stride);
-      }
+      int64_t at = (int64_t)i * stride + (sx + nx * (sy + ny * sz));
+      if (BB == LBM_HALFWAY && i != 0 && ((lk >> i) & 1u)) at = (int64_t)Vel::opp[i] * stride + n;
       f[i] = ST::load(src[at], k.inv_scale);
     }
     if (solid) {
       if (BB == LBM_FULLWAY) {
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-          __builtin_nontemporal_store(ST::store(f[Vel::opp[i]], k.scale),
-                                      &dst[slot<LAYOUT>(n, i, stride)]);
+          __builtin_nontemporal_store(ST::store(f[Vel::opp[i]], k.scale, sr_key(n, i, k.step)),
+                                      &dst[(int64_t)i * stride + n]);
       }
       continue;
     }
     trt_collide<R, ST::kShifted>(f, k);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-      __builtin_nontemporal_store(ST::store(f[i], k.scale), &dst[slot<LAYOUT>(n, i, stride)]);
+      __builtin_nontemporal_store(ST::store(f[i], k.scale, sr_key(n, i, k.step)),
+                                  &dst[(int64_t)i * stride + n]);
+  }
+}
+
+// The 9 source rows of a pull, as (c_y, c_z) of the directions they supply.
+struct SrcRows {
+  static constexpr int cy[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+  static constexpr int cz[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+};
+
+template <class ST, int BB>
+__global__ void __launch_bounds__(1024)
+k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
+            const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx,
+            int ny, int nz, Collide<typename ST::R> k) {
+  using T = typename ST::T;
+  using R = typename ST::R;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* sm = reinterpret_cast<T*>(lds_raw);
+  const int row = blockIdx.x;
+  const int y = row % ny;
+  const int z = row / ny;
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+  const int B = blockDim.x;
+  const int t = threadIdx.x;
+  for (int x0 = 0; x0 < nx; x0 += B) {
+    const int seg = nx - x0 < B ? nx - x0 : B;
+    const bool active = t < seg;
+    const int x = x0 + t;
+    R f[Q];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      const int dy = SrcRows::cy[r], dz = SrcRows::cz[r];
+      const int sy = dy == 1 ? ym : (dy == -1 ? yp : y);
+      const int sz = dz == 1 ? zm : (dz == -1 ? zp : z);
+      const int64_t rbase = (int64_t)(sy + ny * sz) * nx;
+      const int nrec = seg + 2;  // records x0-1 .. x0+seg of the source row
+      __syncthreads();
+      for (int e = t; e < nrec * Q; e += B) {
+        const int rr = e / Q;
+        const int i = e - rr * Q;
+        int xs = x0 - 1 + rr;
+        xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+        sm[e] = src[(rbase + xs) * Q + i];
+      }
+      __syncthreads();
+      if (active) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          if (Vel::cy[i] == dy && Vel::cz[i] == dz)
+            f[i] = ST::load(sm[(t + 1 - Vel::cx[i]) * Q + i], k.inv_scale);
+      }
+    }
+    const int64_t n = (int64_t)row * nx + x;
+    bool solid = false;
+    if (active) {
+      if (BB == LBM_HALFWAY) {
+        const uint32_t lk = links[n];
+        solid = (lk & 1u) != 0;
+        if (!solid && (lk >> 1)) {
+#pragma unroll
+          for (int i = 1; i < Q; ++i)
+            if ((lk >> i) & 1u) f[i] = ST::load(src[n * Q + Vel::opp[i]], k.inv_scale);
+        }
+      } else {
+        solid = mask[n] != 0;
+      }
+      if (!solid) {
+        trt_collide<R, ST::kShifted>(f, k);
+      } else if (BB == LBM_FULLWAY) {
+        R g[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) g[i] = f[Vel::opp[i]];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = g[i];
+      } else {
+        // half-way solids hold no state; keep their slots at the rest value
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = ST::kShifted ? R(0) : R(weight(i));
+      }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) sm[t * Q + i] = ST::store(f[i], k.scale, sr_key((uint32_t)n, i, k.step));
+    }
+    __syncthreads();
+    T* out = dst + ((int64_t)row * nx + x0) * Q;
+    for (int e = t; e < seg * Q; e += B) __builtin_nontemporal_store(sm[e], &out[e]);
   }
 }
 
@@ -88,11 +187,40 @@ k_sweep_list(const typename ST::T* __restrict__ src, typename ST::T* __restrict_
   trt_collide<R, ST::kShifted>(f, k);
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    __builtin_nontemporal_store(ST::store(f[i], k.scale), &dst[(int64_t)i * stride + n]);
+    __builtin_nontemporal_store(ST::store(f[i], k.scale, sr_key(n, i, k.step)),
+                                &dst[(int64_t)i * stride + n]);
+}
+
+// Link words for half-way bounce-back on the full array: bit 0 = the node is
+// solid, bit i (1..18) = the pull source x - c_i is solid.
+__global__ void k_build_links(const uint8_t* __restrict__ mask, uint32_t* __restrict__ links,
+                              int nx, int ny, int nz) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (n >= N) return;
+  const int x = (int)(n % nx);
+  const int64_t r = n / nx;
+  const int y = (int)(r % ny), z = (int)(r / ny);
+  uint32_t w = mask[n] != 0 ? 1u : 0u;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int sx = wrap_sub(x, Vel::cx[i], nx);
+    const int sy = wrap_sub(y, Vel::cy[i], ny);
+    const int sz = wrap_sub(z, Vel::cz[i], nz);
+    if (mask[sx + (int64_t)nx * (sy + (int64_t)ny * sz)] != 0) w |= 1u << i;
+  }
+  links[n] = w;
+}
+
+hipError_t launch_build_links(lbm_ctx* c) {
+  const int64_t N = c->s.n_nodes;
+  hipLaunchKernelGGL(k_build_links, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, c->stream,
+                     c->b.mask, c->b.links, c->p.nx, c->p.ny, c->p.nz);
+  return hipGetLastError();
 }
 
 template <typename R>
-static Collide<R> make_collide(const lbm_params& p) {
+static Collide<R> make_collide(const lbm_params& p, int64_t step) {
   const double tm = 0.5 + p.magic_lambda / (p.tau_plus - 0.5);
   Collide<R> k;
   k.lp = (R)(1.0 / p.tau_plus);
@@ -102,7 +230,8 @@ static Collide<R> make_collide(const lbm_params& p) {
   k.gx = (R)p.g[0];
   k.gy = (R)p.g[1];
   k.gz = (R)p.g[2];
-  if (p.storage == LBM_F16_SHIFTED) {
+  k.step = (uint32_t)step;
+  if (p.storage == LBM_F16_SHIFTED || p.storage == LBM_F16_SHIFTED_SR) {
     k.scale = (R)ldexp(1.0, p.f16_scale_log2);
     k.inv_scale = (R)ldexp(1.0, -p.f16_scale_log2);
   } else {
@@ -112,36 +241,57 @@ static Collide<R> make_collide(const lbm_params& p) {
   return k;
 }
 
+// Dynamic LDS of a sweep launch: what the kernel needs, raised so that at
+// most cu_slots workgroups fit on one compute unit when a cap is set.
+static size_t sweep_lds(const lbm_ctx* c, size_t need) {
+  if (c->p.cu_slots > 0) {
+    size_t cap = (size_t)(kLdsPerCU / c->p.cu_slots) & ~(size_t)255;
+    if (cap > need) return cap;
+  }
+  return need;
+}
+
+size_t aos_lds_bytes(const lbm_ctx* c, int blk) {
+  const int es = c->p.storage == LBM_F64 ? 8 : (c->p.storage == LBM_F32_SHIFTED ? 4 : 2);  // F16: 2
+  return (size_t)(blk + 2) * Q * es;
+}
+
 template <class ST>
 static hipError_t sweep_typed(lbm_ctx* c, const void* src, void* dst) {
   using T = typename ST::T;
   const lbm_params& p = c->p;
-  const auto k = make_collide<typename ST::R>(p);
+  const auto k = make_collide<typename ST::R>(p, c->step);
   const T* s = (const T*)src;
   T* d = (T*)dst;
   if (p.addressing == LBM_LIST) {
     const int nf = (int)c->s.n_fluid;
     if (nf == 0) return hipSuccess;
     const int blk = c->block;
-    hipLaunchKernelGGL(k_sweep_list<ST>, dim3((nf + blk - 1) / blk), dim3(blk), 0, c->stream,
-                       s, d, c->b.adj, nf, c->s.stride, k);
+    hipLaunchKernelGGL(k_sweep_list<ST>, dim3((nf + blk - 1) / blk), dim3(blk), sweep_lds(c, 0),
+                       c->stream, s, d, c->b.adj, nf, c->s.stride, k);
     return hipGetLastError();
   }
   int blk = c->block;
   const int nx_r = ((p.nx + 63) / 64) * 64;
   if (blk > nx_r) blk = nx_r;
   const dim3 grid((unsigned)p.ny * (unsigned)p.nz), block(blk);
-#define LBM_LAUNCH(LAY, BB)                                                                   \
-  hipLaunchKernelGGL((k_sweep_direct<ST, LAY, BB>), grid, block, 0, c->stream, s, d, c->b.mask, \
-                     p.nx, p.ny, p.nz, c->s.stride, k)
   if (p.layout == LBM_SOA) {
-    if (p.bounce == LBM_FULLWAY) LBM_LAUNCH(LBM_SOA, LBM_FULLWAY);
-    else LBM_LAUNCH(LBM_SOA, LBM_HALFWAY);
+    const size_t lds = sweep_lds(c, 0);
+    if (p.bounce == LBM_FULLWAY)
+      hipLaunchKernelGGL((k_sweep_soa<ST, LBM_FULLWAY>), grid, block, lds, c->stream, s, d,
+                         c->b.mask, c->b.links, p.nx, p.ny, p.nz, c->s.stride, k);
+    else
+      hipLaunchKernelGGL((k_sweep_soa<ST, LBM_HALFWAY>), grid, block, lds, c->stream, s, d,
+                         c->b.mask, c->b.links, p.nx, p.ny, p.nz, c->s.stride, k);
   } else {
-    if (p.bounce == LBM_FULLWAY) LBM_LAUNCH(LBM_AOS, LBM_FULLWAY);
-    else LBM_LAUNCH(LBM_AOS, LBM_HALFWAY);
+    const size_t lds = sweep_lds(c, aos_lds_bytes(c, blk));
+    if (p.bounce == LBM_FULLWAY)
+      hipLaunchKernelGGL((k_sweep_aos<ST, LBM_FULLWAY>), grid, block, lds, c->stream, s, d,
+                         c->b.mask, c->b.links, p.nx, p.ny, p.nz, k);
+    else
+      hipLaunchKernelGGL((k_sweep_aos<ST, LBM_HALFWAY>), grid, block, lds, c->stream, s, d,
+                         c->b.mask, c->b.links, p.nx, p.ny, p.nz, k);
   }
-#undef LBM_LAUNCH
   return hipGetLastError();
 }
 
@@ -149,7 +299,8 @@ hipError_t launch_sweep(lbm_ctx* c, const void* src, void* dst) {
   switch (c->p.storage) {
     case LBM_F64: return sweep_typed<StoreF64>(c, src, dst);
     case LBM_F32_SHIFTED: return sweep_typed<StoreF32Shifted>(c, src, dst);
-    default: return sweep_typed<StoreF16Shifted>(c, src, dst);
+    case LBM_F16_SHIFTED: return sweep_typed<StoreF16Shifted>(c, src, dst);
+    default: return sweep_typed<StoreF16ShiftedSR>(c, src, dst);
   }
 }
 

@@ -19,16 +19,16 @@ LIB_PATH = os.path.join(HERE, "_lib", "liblbm.so")
 
 SOA, AOS = 0, 1
 DIRECT, LIST = 0, 1
-F64, F32_SHIFTED, F16_SHIFTED = 0, 1, 2
+F64, F32_SHIFTED, F16_SHIFTED, F16_SHIFTED_SR = 0, 1, 2, 3
 FULLWAY, HALFWAY = 0, 1
 VERIFY_SLAB, VERIFY_DUCT, VERIFY_REFERENCE = 0, 1, 2
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, ENONFINITE, ENOTCONV = 0, -1, -2, -3, -4, -5, -6
 
 _LAYOUTS = {"soa": SOA, "aos": AOS}
 _ADDR = {"direct": DIRECT, "list": LIST}
-_STORAGE = {"f64": F64, "f32s": F32_SHIFTED, "f16s": F16_SHIFTED}
+_STORAGE = {"f64": F64, "f32s": F32_SHIFTED, "f16s": F16_SHIFTED, "f16sr": F16_SHIFTED_SR}
 _BOUNCE = {"fullway": FULLWAY, "halfway": HALFWAY}
-ELEM_BYTES = {F64: 8, F32_SHIFTED: 4, F16_SHIFTED: 2}
+ELEM_BYTES = {F64: 8, F32_SHIFTED: 4, F16_SHIFTED: 2, F16_SHIFTED_SR: 2}
 
 
 class Params(ctypes.Structure):
@@ -36,7 +36,8 @@ class Params(ctypes.Structure):
                 ("layout", ctypes.c_int32), ("addressing", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("bounce", ctypes.c_int32),
                 ("f16_scale_log2", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("tau_plus", ctypes.c_double),
+                ("pad", ctypes.c_int32), ("cu_slots", ctypes.c_int32),
+                ("tau_plus", ctypes.c_double),
                 ("magic_lambda", ctypes.c_double), ("g", ctypes.c_double * 3)]
 
 
@@ -45,7 +46,8 @@ class Sizes(ctypes.Structure):
                 ("n_sites", ctypes.c_int64), ("stride", ctypes.c_int64),
                 ("pdf_bytes", ctypes.c_int64), ("mask_bytes", ctypes.c_int64),
                 ("adj_bytes", ctypes.c_int64), ("fluid_index_bytes", ctypes.c_int64),
-                ("node_map_bytes", ctypes.c_int64), ("u_prev_bytes", ctypes.c_int64),
+                ("node_map_bytes", ctypes.c_int64), ("links_bytes", ctypes.c_int64),
+                ("u_prev_bytes", ctypes.c_int64),
                 ("scratch_bytes", ctypes.c_int64), ("bytes_per_update", ctypes.c_double)]
 
 
@@ -53,7 +55,8 @@ class Buffers(ctypes.Structure):
     _fields_ = [("pdf_a", ctypes.c_void_p), ("pdf_b", ctypes.c_void_p),
                 ("mask", ctypes.c_void_p), ("adj", ctypes.c_void_p),
                 ("fluid_index", ctypes.c_void_p), ("node_map", ctypes.c_void_p),
-                ("u_prev", ctypes.c_void_p), ("scratch", ctypes.c_void_p)]
+                ("links", ctypes.c_void_p), ("u_prev", ctypes.c_void_p),
+                ("scratch", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -131,7 +134,7 @@ def _check(code, where):
 
 def make_params(shape, tau_plus=0.8, magic=3.0 / 16.0, g=(0.0, 0.0, 0.0), layout="soa",
                 addressing="direct", storage="f64", bounce="fullway", f16_scale_log2=14,
-                block=0, pad=-1) -> Params:
+                block=0, pad=-1, cu_slots=0) -> Params:
     nz, ny, nx = shape
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
@@ -142,6 +145,7 @@ def make_params(shape, tau_plus=0.8, magic=3.0 / 16.0, g=(0.0, 0.0, 0.0), layout
     p.f16_scale_log2 = f16_scale_log2
     p.block = block
     p.pad = pad
+    p.cu_slots = cu_slots
     p.tau_plus = tau_plus
     p.magic_lambda = magic
     p.g[0], p.g[1], p.g[2] = (float(v) for v in g)
@@ -193,6 +197,8 @@ class Lattice:
             self._t["adj"] = alloc(s.adj_bytes)
             self._t["fluid_index"] = alloc(s.fluid_index_bytes)
             self._t["node_map"] = alloc(s.node_map_bytes)
+        if s.links_bytes > 0:
+            self._t["links"] = alloc(s.links_bytes)
         if residual:
             self._t["u_prev"] = alloc(s.u_prev_bytes)
         b = Buffers()
@@ -244,6 +250,34 @@ class Lattice:
             out["rho"] = rho
             out["u"] = u.view(3, self.n_nodes)
         return out
+
+    def run_to_steady(self, tol: float, check_every: int = 100, max_steps: int = 1_000_000,
+                      plateau_checks: int = 0):
+        """Step until the velocity residual ||u^t - u^(t-check_every)|| / ||u^t||
+        (FP64, fluid nodes) falls below ``tol``.  With ``plateau_checks`` > 0,
+        also stop when the residual has not fallen below half of its earlier
+        minimum for that many consecutive checks (a precision floor).
+        Returns (steps, residual, reason) with reason in {"converged",
+        "plateau", "max_steps"}."""
+        self.macroscopic()
+        steps = 0
+        best = float("inf")
+        since_best = 0
+        r = float("inf")
+        while steps < max_steps:
+            self.step(check_every)
+            steps += check_every
+            r = self.macroscopic()["residual"]
+            if r < tol:
+                return steps, r, "converged"
+            if r < 0.5 * best:
+                best = r
+                since_best = 0
+            else:
+                since_best += 1
+                if plateau_checks and since_best >= plateau_checks:
+                    return steps, r, "plateau"
+        return steps, r, "max_steps"
 
     def verify(self, kind: int, ref=None):
         r = VerifyResult()

@@ -1,0 +1,109 @@
+"""Shifted low-precision storage (PDFs stored as f - w in FP32, or in FP16
+scaled by 2^s, collision in FP32, reductions in FP64): velocity error of the
+steady channel flow against the FP64 oracle.
+
+The oracle runs on the x-invariant cross-section of the channel (nx = 1):
+with a uniform start and x-periodicity the duct flow does not depend on x,
+so that small run gives the full lattice's velocity field exactly.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1711_11468_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+PHYS = dict(tau_plus=0.8, magic=3 / 16, g=(1e-6, 0.0, 0.0))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1711_11468_amd import lbm
+    lbm.load()
+    return lbm
+
+
+def _oracle_u(ny, nz, nx, steps=None, tol=None):
+    """Oracle velocity [3][N] of the nx x ny x nz channel: after `steps`
+    updates, or at steady state (residual < tol)."""
+    m1 = I.channel_mask(1, ny, nz)
+    f = O.rest_state(m1, 0)
+    if steps is not None:
+        f = O.run(m1, f, steps, PHYS["tau_plus"], PHYS["magic"], PHYS["g"], 0)
+    else:
+        f, _, _ = O.run_to_steady(m1, f, PHYS["tau_plus"], PHYS["magic"], PHYS["g"], 0, tol, 500)
+    u = O.macroscopic(m1, f, PHYS["g"])[1].reshape(nz, ny, 1, 3)
+    u = np.broadcast_to(u, (nz, ny, nx, 3)).reshape(-1, 3)
+    return np.ascontiguousarray(u.T)
+
+
+@pytest.fixture(scope="module")
+def steady_ref():
+    return _oracle_u(32, 32, 64, tol=1e-11)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-5), ("f32s", 1e-5), ("f16sr", 1e-3)])
+def test_steady_channel_error(L, steady_ref, storage, tol):
+    """64x32x32 channel (the parity configuration) run to residual 1e-6:
+    relative L2 velocity error against the converged FP64 oracle field."""
+    import torch
+    mask = I.channel_mask(64, 32, 32)
+    lat = L.Lattice(mask, storage=storage, **PHYS)
+    steps, r, why = lat.run_to_steady(1e-6, max_steps=40000, plateau_checks=30)
+    ref = torch.from_numpy(steady_ref.reshape(-1)).to(lat.device)
+    v = lat.verify(L.VERIFY_REFERENCE, ref)
+    print(storage, steps, r, why, v)
+    assert why in ("converged", "plateau")
+    assert v["rel_l2"] <= tol
+    if storage != "f16sr":
+        assert why == "converged"
+
+
+def test_f16_nearest_rounding_stalls(L, steady_ref):
+    """Round-to-nearest half storage loses the sub-ulp increments of the slow
+    approach to steady state: the residual falls below 1e-6 while the flow
+    is still percents away from the steady profile.  Stochastic rounding
+    keeps the expected increment and reaches the profile."""
+    import torch
+    mask = I.channel_mask(64, 32, 32)
+    errs = {}
+    for storage in ("f16s", "f16sr"):
+        lat = L.Lattice(mask, storage=storage, **PHYS)
+        lat.run_to_steady(1e-6, max_steps=40000, plateau_checks=30)
+        ref = torch.from_numpy(steady_ref.reshape(-1)).to(lat.device)
+        errs[storage] = lat.verify(L.VERIFY_REFERENCE, ref)["rel_l2"]
+    print(errs)
+    assert errs["f16s"] > 5 * errs["f16sr"]
+
+
+@pytest.mark.parametrize("storage,tol", [("f32s", 1e-5), ("f16s", 1e-2), ("f16sr", 1e-3)])
+def test_equal_step_error(L, storage, tol):
+    """Same number of updates (1500) in low precision and in the FP64
+    oracle: isolates the storage rounding from the iteration error."""
+    import torch
+    steps = 1500
+    ref = _oracle_u(32, 32, 64, steps=steps)
+    mask = I.channel_mask(64, 32, 32)
+    lat = L.Lattice(mask, storage=storage, **PHYS)
+    lat.step(steps)
+    v = lat.verify(L.VERIFY_REFERENCE, torch.from_numpy(ref.reshape(-1)).to(lat.device))
+    print(storage, v)
+    assert v["rel_l2"] <= tol
+
+
+@pytest.mark.parametrize("storage", ["f32s", "f16s", "f16sr"])
+def test_shifted_mass_conservation(L, storage):
+    """Shifted storage keeps the lattice mass to FP64-reduction accuracy
+    plus the storage rounding of the rest state (exactly zero)."""
+    mask = I.channel_mask(40, 20, 18)
+    lat = L.Lattice(mask, storage=storage, **PHYS)
+    s0 = lat.macroscopic()
+    lat.step(300)
+    s1 = lat.macroscopic()
+    assert abs(s0["mass"] - mask.size) <= 1e-12 * mask.size
+    rel = abs(s1["mass"] - s0["mass"]) / s0["mass"]
+    assert rel <= (1e-9 if storage == "f32s" else 1e-5)
