@@ -116,6 +116,27 @@ def membench(lat, reps=20):
     return out
 
 
+def warm_vs_cold(n=128, seeds=(100000, 100001, 100002)):
+    """Time to steady state (residual 1e-6) on held-out 128^3 porous boxes,
+    cold start versus the learned warm start (inference included)."""
+    from paper_1711_11468_amd import warmstart as WS
+    from paper_1711_11468_amd.surrogate import UNet
+    path = os.path.join(ROOT, "paper_1711_11468_amd", "weights", "unet_porous64.npz")
+    if not os.path.exists(path):
+        return None
+    net = UNet.load(path)
+    rows = [WS.compare(net, s, n) for s in seeds]
+    log("warm vs cold: %s" % [(r["cold_steps"], r["warm_steps"]) for r in rows])
+    return {"workload": "porous box %d^3, overlapping spheres r in [4,8], porosity U[0.35,0.7], "
+                        "list FP64, tau+=0.8, Lambda=3/16, g_x=1e-6, residual 1e-6" % n,
+            "cold_steps_median": float(np.median([r["cold_steps"] for r in rows])),
+            "warm_steps_median": float(np.median([r["warm_steps"] for r in rows])),
+            "cold_s_median": float(np.median([r["cold_s"] for r in rows])),
+            "warm_s_median": float(np.median([r["warm_s"] for r in rows])),
+            "step_speedup_median": float(np.median([r["cold_steps"] / r["warm_steps"] for r in rows])),
+            "prediction_rel_l2_median": float(np.median([r["prediction_rel_l2"] for r in rows]))}
+
+
 def cpu_baseline():
     """The oracle (single-threaded C, as it stands) on a bounded sample of
     the headline workload: a 16-node-long section of the same 512 x 512
@@ -184,6 +205,7 @@ def main():
             del lat
             torch.cuda.empty_cache()
 
+    steady = None if args.headline_only else warm_vs_cold()
     cpu = None if args.no_cpu else cpu_baseline()
     achieved = head["achieved_gbs"]
     line = {
@@ -212,6 +234,7 @@ def main():
                      "frac_of_copy19nt": round(achieved / mb["copy-19-nt"], 4)},
         "membench_gbs": mb,
         "variants": variants,
+        "steady_state": steady,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -184,11 +184,13 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params,
                       const uint8_t* mask_host, const lbm_buffers* bufs,
                       void* stream);
 
-/* Initialise the state to equilibrium f = e(rho, u) node by node (fluid
- * nodes; solids get the rest state).  rho_dev: N doubles or NULL (rho = 1);
- * u_dev: 3*N doubles, component-major [3][N], or NULL (u = 0).  Both are
- * device pointers indexed by full node index.  Resets the step counter and
- * the residual history.  Errors: EINVAL, EDEVICE. */
+/* Initialise the state to equilibrium node by node so that the state's
+ * density and velocity (as lbm_macroscopic reports them) are rho and u:
+ * f = e(rho, u - g/(2 rho)) on fluid nodes, since the velocity of a state
+ * is (sum c f + g/2)/rho; solids get the rest state.  rho_dev: N doubles or
+ * NULL (rho = 1); u_dev: 3*N doubles, component-major [3][N], or NULL
+ * (u = 0).  Both are device pointers indexed by full node index.  Resets
+ * the step counter and the residual history.  Errors: EINVAL, EDEVICE. */
 int lbm_init_fields(lbm_ctx* ctx, const double* rho_dev, const double* u_dev);
 
 /* Enqueue n fused stream-collide updates (one kernel launch each, source

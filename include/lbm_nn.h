@@ -1,0 +1,118 @@
+/*
+ * lbm_nn.h - C ABI of the learned warm start: BF16 MFMA kernels for a small
+ * 3D convolutional network that maps a solid mask (and the driving force
+ * direction) to the steady velocity field of the lattice Boltzmann solver.
+ * The network is not part of the paper; it provides initial states for the
+ * solver, which stays the judge of the steady state (it runs from the
+ * predicted equilibrium until its own residual criterion is met).
+ *
+ * Conventions:
+ *  - Tensors are channels-last (NDHWC): element (b, z, y, x, c) at
+ *    (((b*D + z)*H + y)*W + x)*C + c.  bf16 tensors are uint16_t bit
+ *    patterns (IEEE binary32 upper half, round-to-nearest-even on
+ *    conversion); accumulation is float32 in the MFMA units
+ *    (v_mfma_f32_16x16x16_bf16).
+ *  - Convolution weights are [taps][c_out][c_in] bf16, taps = 27
+ *    (3x3x3, index (kz*3 + ky)*3 + kx, offsets -1..1) or 1 (1x1x1).
+ *    Padding is circular (the lattice is periodic).  With stride 2 the
+ *    output voxel p reads input voxels 2p + k - 1.
+ *  - Channel counts c_in and c_out are multiples of 16 (pad with zero
+ *    channels/weights), (c_in/16)*(c_out/16) <= 32; the voxel counts of
+ *    the input and output grids are multiples of 16.
+ *  - All device pointers are caller-owned; every call only enqueues work on
+ *    `stream` (a hipStream_t) and returns 0 or a negative code
+ *    (-1 invalid argument, -4 HIP error; see lbm_last_error()).
+ *  - Reductions (weight gradients, bias gradients, the loss) are split
+ *    into fixed chunks and summed in a fixed order: results are
+ *    deterministic run to run.
+ */
+#ifndef LBM_NN_MI355X_H
+#define LBM_NN_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t batch;
+  int32_t d, h, w;     /* input grid                                       */
+  int32_t c_in;        /* input channels, multiple of 16                   */
+  int32_t c_out;       /* output channels computed, multiple of 16 (<= 128)*/
+  int32_t c_store;     /* output channels written (<= c_out), forward only */
+  int32_t stride;      /* 1 or 2 (taps = 27 only); output grid = input/s   */
+  int32_t taps;        /* 27 or 1                                          */
+  int32_t act;         /* 0: none, 1: leaky ReLU                           */
+  float slope;         /* leaky ReLU slope for negative inputs             */
+  int32_t out_f32;     /* forward output type: 1 float32, 0 bf16          */
+} nn_conv_desc;
+
+/* y = act(conv(x, w) + bias).  x: [B][D][H][W][c_in] bf16; w: [taps][c_out]
+ * [c_in] bf16; bias: c_out float32 or NULL; y: [B][D/s][H/s][W/s][c_store],
+ * bf16 or float32. */
+int nn_conv3d_fwd(const nn_conv_desc* d, const uint16_t* x, const uint16_t* w,
+                  const float* bias, void* y, void* stream);
+
+/* Data gradient: dx (+)= conv^T(dy, w), the gradient with respect to the
+ * input of the convolution given dy, the gradient with respect to its
+ * pre-activation output ([B][D/s][H/s][W/s][c_out] bf16).  dx: [B][D][H][W]
+ * [c_in] float32; accumulate != 0 adds to dx.  w_t: workspace of
+ * taps*c_in*c_out bf16 (the transposed weights). */
+int nn_conv3d_dgrad(const nn_conv_desc* d, const uint16_t* dy, const uint16_t* w,
+                    uint16_t* w_t, float* dx, int32_t accumulate, void* stream);
+
+/* Weight and bias gradients: dw[taps][c_out][c_in] = sum over output voxels
+ * of dy (x) x at the tap offset; db[c_out] = sum of dy (db may be NULL).
+ * Both float32, overwritten.  workspace: nn_conv3d_wgrad_workspace() bytes. */
+int nn_conv3d_wgrad(const nn_conv_desc* d, const uint16_t* x, const uint16_t* dy, float* dw,
+                    float* db, float* workspace, void* stream);
+int64_t nn_conv3d_wgrad_workspace(const nn_conv_desc* d);
+
+/* dy_pre = bf16(dx * (y > 0 ? 1 : slope)) for n elements (y: the bf16
+ * leaky ReLU output, whose sign is that of its input). */
+int nn_lrelu_bwd(const float* dx, const uint16_t* y, uint16_t* dy_pre, int64_t n, float slope,
+                 void* stream);
+
+/* cat[b,z,y,x] = (coarse[b,z/2,y/2,x/2][0..c1), skip[b,z,y,x][0..c2)):
+ * nearest-neighbour upsampling by 2 and channel concatenation; (d, h, w)
+ * is the fine grid. */
+int nn_up_concat(const uint16_t* coarse, const uint16_t* skip, uint16_t* cat, int32_t batch,
+                 int32_t d, int32_t h, int32_t w, int32_t c1, int32_t c2, void* stream);
+
+/* Backward of nn_up_concat: dcoarse = sum over the 8 fine children of the
+ * first c1 channels of dcat; dskip = the last c2 channels (both
+ * overwritten). */
+int nn_split_down(const float* dcat, float* dcoarse, float* dskip, int32_t batch, int32_t d,
+                  int32_t h, int32_t w, int32_t c1, int32_t c2, void* stream);
+
+/* Masked mean squared error over fluid voxels (mask == 0) of pred and
+ * target ([n][3] float32): loss (float32, one value, device) and its
+ * gradient written as the bf16 pre-activation gradient of the 1x1x1 head,
+ * dy[n][16] (channels 3..15 zero).  workspace: 4096 floats. */
+int nn_masked_mse(const float* pred, const float* target, const uint8_t* mask, int64_t n,
+                  uint16_t* dy, float* loss, float* workspace, void* stream);
+
+/* Adam step (Kingma and Ba) on float32 master weights; writes the bf16
+ * copy used by the kernels.  t >= 1 is the step number. */
+int nn_adam_step(float* param, const float* grad, float* m, float* v, uint16_t* param_bf16,
+                 int64_t n, float lr, float beta1, float beta2, float eps, int32_t t,
+                 void* stream);
+
+/* Network input from a solid mask: x[n][c_pad] bf16 with channel 0 = solid
+ * (1/0), channel 1 = fluid (1/0), other channels zero. */
+int nn_prepare_input(const uint8_t* mask, uint16_t* x, int64_t n, int32_t c_pad, void* stream);
+
+/* Velocity for the solver: u[a*n + i] = scale * pred[i][a] on fluid
+ * voxels, 0 on solids (float64, component-major [3][n]). */
+int nn_velocity_out(const float* pred, const uint8_t* mask, double scale, double* u, int64_t n,
+                    void* stream);
+
+/* float32 -> bf16 (round to nearest even), n elements. */
+int nn_to_bf16(const float* src, uint16_t* dst, int64_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_NN_MI355X_H */

@@ -1,0 +1,69 @@
+"""CPU float64 reference of the warm-start network (TEST INFRASTRUCTURE ONLY).
+
+Plain PyTorch CPU operations in float64: ``conv3d`` on circularly padded
+input, leaky ReLU, nearest-neighbour upsampling, concatenation, masked mean
+squared error, with gradients from autograd.  It shares no code with the
+GPU kernels; it takes the same weights (rounded to bf16 by the caller when
+comparing with the bf16 kernels) in the layout [taps][c_out][c_in] and
+channels-last activations [B][D][H][W][C].
+"""
+from __future__ import annotations
+
+import torch
+import torch.nn.functional as F
+
+SLOPE = 0.1
+CH = (16, 32, 64, 64)
+
+
+def to_ncdhw(x):
+    return x.permute(0, 4, 1, 2, 3)
+
+
+def to_ndhwc(x):
+    return x.permute(0, 2, 3, 4, 1)
+
+
+def conv(x, w, b, stride=1, taps=27, act=True, slope=SLOPE):
+    """x: [B,D,H,W,Ci]; w: [taps][Co][Ci]; b: [Co] or None -> [B,D',H',W',Co]."""
+    co, ci = w.shape[1], w.shape[2]
+    xt = to_ncdhw(x)
+    if taps == 27:
+        wt = w.reshape(3, 3, 3, co, ci).permute(3, 4, 0, 1, 2)
+        y = F.conv3d(F.pad(xt, (1, 1, 1, 1, 1, 1), mode="circular"), wt, b, stride=stride)
+    else:
+        y = F.conv3d(xt, w.reshape(co, ci, 1, 1, 1), b)
+    if act:
+        y = F.leaky_relu(y, slope)
+    return to_ndhwc(y)
+
+
+def up_concat(coarse, skip):
+    up = to_ndhwc(F.interpolate(to_ncdhw(coarse), scale_factor=2, mode="nearest"))
+    return torch.cat([up, skip], dim=-1)
+
+
+def unet(x, params):
+    """params: dict name -> (w, b) float64 tensors, names as in the GPU net."""
+    def c(name, t, **kw):
+        w, b = params[name]
+        return conv(t, w, b, **kw)
+    e0 = c("e0", c("e0a", x))
+    e1 = c("e1", c("e1a", c("d1", e0, stride=2)))
+    e2 = c("e2", c("e2a", c("d2", e1, stride=2)))
+    e3 = c("e3", c("e3a", c("d3", e2, stride=2)))
+    u2 = c("u2", c("u2a", up_concat(e3, e2)))
+    u1 = c("u1", c("u1a", up_concat(u2, e1)))
+    u0 = c("u0", c("u0a", up_concat(u1, e0)))
+    return c("head", u0, taps=1, act=False)[..., :3]
+
+
+def masked_mse(pred, target, fluid):
+    """Mean over fluid voxels and the 3 components of (pred - target)^2."""
+    d = (pred - target)[fluid]
+    return (d * d).sum() / (3.0 * fluid.sum())
+
+
+def bf16_round(t):
+    """Round float64 values to bf16 (round to nearest even) and back."""
+    return t.to(torch.float32).to(torch.bfloat16).to(torch.float64)

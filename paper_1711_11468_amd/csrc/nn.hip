@@ -1,0 +1,709 @@
+// nn.hip - BF16 MFMA kernels of the learned warm start (ABI: include/lbm_nn.h).
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x16_bf16: one wavefront
+// owns a 16 x 16 tile of the (voxel x channel) output and walks the K
+// dimension (taps x input-channel chunks of 16).  Operand layout of the
+// instruction (64 lanes, l = lane): A[i][k] lives in lane i + 16*(k/4),
+// element k%4; B[k][j] in lane j + 16*(k/4), element k%4; the float32 result
+// D[i][j] in lane j + 16*(i/4), element i%4.  Channels-last tensors make the
+// 4 consecutive K elements of a lane 8 contiguous bytes.
+#include <stdint.h>
+
+#include "../../include/lbm_nn.h"
+#include "internal.hpp"
+
+namespace lbm {
+namespace nn {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);                      // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+struct Geom {
+  int B, D, H, W;     // input grid
+  int Do, Ho, Wo;     // output grid
+  int ci, co, cstore;
+  int act;
+  float slope;
+  int64_t m_out;      // B*Do*Ho*Wo
+  int64_t m_in;       // B*D*H*W
+};
+
+__device__ __forceinline__ void tap_offsets(int tap, int taps, int& dz, int& dy, int& dx) {
+  if (taps == 27) {
+    dz = tap / 9 - 1;
+    dy = (tap / 3) % 3 - 1;
+    dx = tap % 3 - 1;
+  } else {
+    dz = dy = dx = 0;
+  }
+}
+
+// ---- forward --------------------------------------------------------------
+template <int STRIDE, int TAPS, int NB, bool OUTF32>
+__global__ void __launch_bounds__(256)
+k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
+           const float* __restrict__ bias, void* __restrict__ y, Geom g) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (v0 >= g.m_out) return;
+  const int row = lane & 15, kq = lane >> 4;
+  // the output voxel of this lane's A row (tiles may span grid rows)
+  int64_t t = v0 + row;
+  const int xo = (int)(t % g.Wo);
+  t /= g.Wo;
+  const int yo = (int)(t % g.Ho);
+  t /= g.Ho;
+  const int zo = (int)(t % g.Do);
+  const int b = (int)(t / g.Do);
+  f4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int tap = 0; tap < TAPS; ++tap) {
+    int dz, dy, dx;
+    tap_offsets(tap, TAPS, dz, dy, dx);
+    const int zi = wrapi(STRIDE * zo + dz, g.D);
+    const int yi = wrapi(STRIDE * yo + dy, g.H);
+    const int xi = wrapi(STRIDE * xo + dx, g.W);
+    const uint16_t* xp = x + ((((int64_t)b * g.D + zi) * g.H + yi) * g.W + xi) * g.ci + 4 * kq;
+    const uint16_t* wp = w + ((int64_t)tap * g.co + row) * g.ci + 4 * kq;
+    for (int c0 = 0; c0 < g.ci; c0 += 16) {
+      const s4 a = *(const s4*)(xp + c0);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const s4 bv = *(const s4*)(wp + (int64_t)nb * 16 * g.ci + c0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[nb], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int co = nb * 16 + row;
+    if (co >= g.cstore) continue;
+    const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t vox = v0 + 4 * kq + r;
+      float v = acc[nb][r] + bb;
+      if (g.act) v = v > 0.f ? v : v * g.slope;
+      if (OUTF32) ((float*)y)[vox * g.cstore + co] = v;
+      else ((uint16_t*)y)[vox * g.cstore + co] = f2bf(v);
+    }
+  }
+}
+
+// ---- data gradient --------------------------------------------------------
+// dx[q] = sum over taps and output voxels p with s*p + off = q of W^T dy[p].
+template <int STRIDE, int TAPS, int NB>
+__global__ void __launch_bounds__(256)
+k_conv_dgrad(const uint16_t* __restrict__ dyp, const uint16_t* __restrict__ wt,
+             float* __restrict__ dxp, int accumulate, Geom g) {
+  const int lane = threadIdx.x & 63;
+  const int64_t q0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (q0 >= g.m_in) return;
+  const int row = lane & 15, kq = lane >> 4;
+  int64_t t = q0 + row;
+  const int xq = (int)(t % g.W);
+  t /= g.W;
+  const int yq = (int)(t % g.H);
+  t /= g.H;
+  const int zq = (int)(t % g.D);
+  const int b = (int)(t / g.D);
+  f4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int tap = 0; tap < TAPS; ++tap) {
+    int dz, dy, dx;
+    tap_offsets(tap, TAPS, dz, dy, dx);
+    const int tz = wrapi(zq - dz, g.D), ty = wrapi(yq - dy, g.H), tx = wrapi(xq - dx, g.W);
+    // stride 2: only even fine coordinates are images of coarse voxels
+    const bool valid = STRIDE == 1 || ((tz | ty | tx) & 1) == 0;
+    const int pz = tz / STRIDE, py = ty / STRIDE, px = tx / STRIDE;
+    const uint16_t* ap = dyp + ((((int64_t)b * g.Do + pz) * g.Ho + py) * g.Wo + px) * g.co + 4 * kq;
+    const uint16_t* bp = wt + ((int64_t)tap * g.ci + row) * g.co + 4 * kq;
+    for (int c0 = 0; c0 < g.co; c0 += 16) {
+      s4 a = valid ? *(const s4*)(ap + c0) : s4{0, 0, 0, 0};
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const s4 bv = *(const s4*)(bp + (int64_t)nb * 16 * g.co + c0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[nb], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int c = nb * 16 + row;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float* o = dxp + (q0 + 4 * kq + r) * g.ci + c;
+      *o = accumulate ? *o + acc[nb][r] : acc[nb][r];
+    }
+  }
+}
+
+__global__ void k_transpose_w(const uint16_t* __restrict__ w, uint16_t* __restrict__ wt, int taps,
+                              int co, int ci) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)taps * co * ci;
+  if (e >= n) return;
+  const int c_in = (int)(e % ci);
+  const int c_out = (int)((e / ci) % co);
+  const int tap = (int)(e / ((int64_t)ci * co));
+  wt[((int64_t)tap * ci + c_in) * co + c_out] = w[e];
+}
+
+// ---- weight gradient ------------------------------------------------------
+// Grid (chunks, taps); each block sums its chunk of output voxels for one
+// tap into all (c_out x c_in) 16x16 tiles, staging dy and the tap-shifted
+// input transposed ([channel][voxel]) in LDS.
+template <int STRIDE, int TAPS, int TPW>
+__global__ void __launch_bounds__(256)
+k_conv_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dyp,
+             float* __restrict__ partial, int64_t chunk, Geom g) {
+  __shared__ __align__(16) uint16_t dyT[128 * 64];
+  __shared__ __align__(16) uint16_t xT[128 * 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tap = blockIdx.y;
+  int dz, dy, dx;
+  tap_offsets(tap, TAPS, dz, dy, dx);
+  const int64_t start = (int64_t)blockIdx.x * chunk;
+  int64_t end = start + chunk;
+  if (end > g.m_out) end = g.m_out;
+  const int nbo = g.co / 16, nbi = g.ci / 16, ntiles = nbo * nbi;
+  const int row = lane & 15, kq = lane >> 4;
+  f4 acc[TPW];
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t p0 = start; p0 < end; p0 += 64) {
+    __syncthreads();
+    for (int e = tid; e < 64 * g.co; e += 256) {
+      const int p = e / g.co, c = e - p * g.co;
+      const int64_t vox = p0 + p;
+      dyT[c * 64 + p] = vox < end ? dyp[vox * g.co + c] : (uint16_t)0;
+    }
+    for (int e = tid; e < 64 * g.ci; e += 256) {
+      const int p = e / g.ci, c = e - p * g.ci;
+      const int64_t vox = p0 + p;
+      uint16_t val = 0;
+      if (vox < end) {
+        int64_t t = vox;
+        const int xo = (int)(t % g.Wo);
+        t /= g.Wo;
+        const int yo = (int)(t % g.Ho);
+        t /= g.Ho;
+        const int zo = (int)(t % g.Do);
+        const int b = (int)(t / g.Do);
+        const int zi = wrapi(STRIDE * zo + dz, g.D), yi = wrapi(STRIDE * yo + dy, g.H),
+                  xi = wrapi(STRIDE * xo + dx, g.W);
+        val = x[((((int64_t)b * g.D + zi) * g.H + yi) * g.W + xi) * g.ci + c];
+      }
+      xT[c * 64 + p] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+      for (int j = 0; j < TPW; ++j) {
+        const int tile = wave + 4 * j;
+        if (tile < ntiles) {
+          const int mo = tile / nbi, ni = tile - mo * nbi;
+          const s4 a = *(const s4*)(&dyT[(mo * 16 + row) * 64 + kk * 16 + 4 * kq]);
+          const s4 bv = *(const s4*)(&xT[(ni * 16 + row) * 64 + kk * 16 + 4 * kq]);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[j], 0, 0, 0);
+        }
+      }
+    }
+  }
+  float* out = partial + ((int64_t)blockIdx.x * TAPS + tap) * g.co * g.ci;
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) {
+    const int tile = wave + 4 * j;
+    if (tile < ntiles) {
+      const int mo = tile / nbi, ni = tile - mo * nbi;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[(mo * 16 + 4 * kq + r) * g.ci + ni * 16 + row] = acc[j][r];
+    }
+  }
+}
+
+// Sum chunk partials in chunk order.
+__global__ void k_sum_chunks(const float* __restrict__ partial, float* __restrict__ out,
+                             int64_t n, int64_t chunks) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int64_t c = 0; c < chunks; ++c) s += partial[c * n + i];
+  out[i] = s;
+}
+
+// Bias gradient partials: block per chunk, fixed-order combination.
+__global__ void __launch_bounds__(256)
+k_bias_partial(const uint16_t* __restrict__ dyp, float* __restrict__ partial, int64_t chunk,
+               int64_t m, int co) {
+  __shared__ float sm[256];
+  const int tid = threadIdx.x;
+  const int groups = 256 / co;
+  const int c = tid % co, gidx = tid / co;
+  const int64_t start = (int64_t)blockIdx.x * chunk;
+  int64_t end = start + chunk;
+  if (end > m) end = m;
+  float s = 0.f;
+  if (gidx < groups)
+    for (int64_t p = start + gidx; p < end; p += groups) s += bf2f(dyp[p * co + c]);
+  sm[tid] = s;
+  __syncthreads();
+  if (tid < co) {
+    float tot = 0.f;
+    for (int k = 0; k < groups; ++k) tot += sm[k * co + tid];
+    partial[(int64_t)blockIdx.x * co + tid] = tot;
+  }
+}
+
+// ---- elementwise ----------------------------------------------------------
+__global__ void k_lrelu_bwd(const float* __restrict__ dx, const uint16_t* __restrict__ y,
+                            uint16_t* __restrict__ d, int64_t n, float slope) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  d[i] = f2bf(bf2f(y[i]) > 0.f ? dx[i] : dx[i] * slope);
+}
+
+__global__ void k_up_concat(const uint16_t* __restrict__ coarse, const uint16_t* __restrict__ skip,
+                            uint16_t* __restrict__ cat, int64_t nvox, int d, int h, int w, int c1,
+                            int c2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ct = c1 + c2;
+  if (e >= nvox * ct) return;
+  const int64_t v = e / ct;
+  const int c = (int)(e - v * ct);
+  if (c < c1) {
+    int64_t t = v;
+    const int xx = (int)(t % w);
+    t /= w;
+    const int yy = (int)(t % h);
+    t /= h;
+    const int zz = (int)(t % d);
+    const int b = (int)(t / d);
+    const int64_t cv = (((int64_t)b * (d / 2) + zz / 2) * (h / 2) + yy / 2) * (w / 2) + xx / 2;
+    cat[e] = coarse[cv * c1 + c];
+  } else {
+    cat[e] = skip[v * c2 + (c - c1)];
+  }
+}
+
+__global__ void k_split_down_coarse(const float* __restrict__ dcat, float* __restrict__ dcoarse,
+                                    int64_t ncoarse, int d, int h, int w, int c1, int c2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ncoarse * c1) return;
+  const int64_t v = e / c1;
+  const int c = (int)(e - v * c1);
+  const int dc = d / 2, hc = h / 2, wc = w / 2;
+  int64_t t = v;
+  const int xc = (int)(t % wc);
+  t /= wc;
+  const int yc = (int)(t % hc);
+  t /= hc;
+  const int zc = (int)(t % dc);
+  const int b = (int)(t / dc);
+  float s = 0.f;
+  for (int k = 0; k < 8; ++k) {
+    const int zz = 2 * zc + (k >> 2), yy = 2 * yc + ((k >> 1) & 1), xx = 2 * xc + (k & 1);
+    const int64_t fv = (((int64_t)b * d + zz) * h + yy) * w + xx;
+    s += dcat[fv * (c1 + c2) + c];
+  }
+  dcoarse[e] = s;
+}
+
+__global__ void k_split_down_skip(const float* __restrict__ dcat, float* __restrict__ dskip,
+                                  int64_t nfine, int c1, int c2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nfine * c2) return;
+  const int64_t v = e / c2;
+  const int c = (int)(e - v * c2);
+  dskip[e] = dcat[v * (c1 + c2) + c1 + c];
+}
+
+// Masked MSE: partial (sum of squared errors, fluid count) per block, then
+// one block combines them in order; the gradient kernel reads the count.
+__global__ void __launch_bounds__(256)
+k_mse_partial(const float* __restrict__ pred, const float* __restrict__ tgt,
+              const uint8_t* __restrict__ mask, int64_t n, float* __restrict__ partial) {
+  __shared__ float s_err[256];
+  __shared__ float s_cnt[256];
+  float e = 0.f, cnt = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (mask[i] == 0) {
+      for (int a = 0; a < 3; ++a) {
+        const float d = pred[i * 3 + a] - tgt[i * 3 + a];
+        e += d * d;
+      }
+      cnt += 1.f;
+    }
+  }
+  s_err[threadIdx.x] = e;
+  s_cnt[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      s_err[threadIdx.x] += s_err[threadIdx.x + off];
+      s_cnt[threadIdx.x] += s_cnt[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = s_err[0];
+    partial[2 * blockIdx.x + 1] = s_cnt[0];
+  }
+}
+
+__global__ void k_mse_final(const float* __restrict__ partial, int nblocks, float* __restrict__ loss,
+                            float* __restrict__ count) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  float e = 0.f, c = 0.f;
+  for (int b = 0; b < nblocks; ++b) {
+    e += partial[2 * b];
+    c += partial[2 * b + 1];
+  }
+  *count = c;
+  *loss = c > 0.f ? e / (3.f * c) : 0.f;
+}
+
+__global__ void k_mse_grad(const float* __restrict__ pred, const float* __restrict__ tgt,
+                           const uint8_t* __restrict__ mask, int64_t n,
+                           const float* __restrict__ count, uint16_t* __restrict__ dy) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * 16) return;
+  const int64_t i = e >> 4;
+  const int c = (int)(e & 15);
+  float gval = 0.f;
+  if (c < 3 && mask[i] == 0) gval = 2.f * (pred[i * 3 + c] - tgt[i * 3 + c]) / (3.f * *count);
+  dy[e] = f2bf(gval);
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ gr, float* __restrict__ m,
+                       float* __restrict__ v, uint16_t* __restrict__ pb, int64_t n, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float g = gr[i];
+  const float mi = b1 * m[i] + (1.f - b1) * g;
+  const float vi = b2 * v[i] + (1.f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / c1, vh = vi / c2;
+  const float pi = p[i] - lr * mh / (sqrtf(vh) + eps);
+  p[i] = pi;
+  pb[i] = f2bf(pi);
+}
+
+__global__ void k_prepare_input(const uint8_t* __restrict__ mask, uint16_t* __restrict__ x,
+                                int64_t n, int cpad) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * cpad) return;
+  const int64_t i = e / cpad;
+  const int c = (int)(e - i * cpad);
+  const bool solid = mask[i] != 0;
+  float v = 0.f;
+  if (c == 0) v = solid ? 1.f : 0.f;
+  if (c == 1) v = solid ? 0.f : 1.f;
+  x[e] = f2bf(v);
+}
+
+__global__ void k_velocity_out(const float* __restrict__ pred, const uint8_t* __restrict__ mask,
+                               double scale, double* __restrict__ u, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool solid = mask[i] != 0;
+  for (int a = 0; a < 3; ++a) u[a * n + i] = solid ? 0.0 : scale * (double)pred[i * 3 + a];
+}
+
+__global__ void k_to_bf16(const float* __restrict__ s, uint16_t* __restrict__ d, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = f2bf(s[i]);
+}
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+static int check_desc(const nn_conv_desc* d) {
+  if (!d) { set_error("descriptor is NULL"); return -1; }
+  if (d->batch < 1 || d->d < 1 || d->h < 1 || d->w < 1) { set_error("bad grid"); return -1; }
+  if (d->c_in < 16 || d->c_in % 16 || d->c_in > 128) { set_error("c_in must be a multiple of 16 in [16,128]"); return -1; }
+  if (d->c_out < 16 || d->c_out % 16 || d->c_out > 128) { set_error("c_out must be a multiple of 16 in [16,128]"); return -1; }
+  if (d->taps != 27 && d->taps != 1) { set_error("taps must be 27 or 1"); return -1; }
+  if (d->stride != 1 && d->stride != 2) { set_error("stride must be 1 or 2"); return -1; }
+  if (d->stride == 2 && (d->taps != 27 || d->d % 2 || d->h % 2 || d->w % 2)) {
+    set_error("stride 2 needs 3x3x3 taps and even grid sizes");
+    return -1;
+  }
+  const int64_t m_in = (int64_t)d->batch * d->d * d->h * d->w;
+  if (m_in % (16 * d->stride * d->stride * d->stride)) {
+    set_error("voxel counts of the input and output grids must be multiples of 16");
+    return -1;
+  }
+  if (d->c_store < 1 || d->c_store > d->c_out) { set_error("bad c_store"); return -1; }
+  if ((d->c_out / 16) * (d->c_in / 16) > 32) { set_error("c_out*c_in exceeds 32 tiles of 16x16"); return -1; }
+  return 0;
+}
+
+static Geom make_geom(const nn_conv_desc* d) {
+  Geom g;
+  g.B = d->batch;
+  g.D = d->d;
+  g.H = d->h;
+  g.W = d->w;
+  g.Do = d->d / d->stride;
+  g.Ho = d->h / d->stride;
+  g.Wo = d->w / d->stride;
+  g.ci = d->c_in;
+  g.co = d->c_out;
+  g.cstore = d->c_store;
+  g.act = d->act;
+  g.slope = d->slope;
+  g.m_out = (int64_t)g.B * g.Do * g.Ho * g.Wo;
+  g.m_in = (int64_t)g.B * g.D * g.H * g.W;
+  return g;
+}
+
+static int64_t wgrad_chunk(const Geom& g, int64_t* chunks) {
+  int64_t c = (g.m_out + 1023) / 1024;
+  if (c > 256) c = 256;
+  if (c < 1) c = 1;
+  int64_t per = (g.m_out + c - 1) / c;
+  per = (per + 63) / 64 * 64;
+  *chunks = (g.m_out + per - 1) / per;
+  return per;
+}
+
+template <int STRIDE, int TAPS, bool F32>
+static void launch_fwd_nb(int nb, const uint16_t* x, const uint16_t* w, const float* bias, void* y,
+                          const Geom& g, hipStream_t s) {
+  const dim3 grid(nblk(g.m_out / 16, 4)), block(256);
+  switch (nb) {
+#define CASE(N) \
+  case N: hipLaunchKernelGGL((k_conv_fwd<STRIDE, TAPS, N, F32>), grid, block, 0, s, x, w, bias, y, g); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+  }
+}
+
+template <int STRIDE, int TAPS>
+static void launch_dgrad_nb(int nb, const uint16_t* dy, const uint16_t* wt, float* dx, int acc,
+                            const Geom& g, hipStream_t s) {
+  const dim3 grid(nblk(g.m_in / 16, 4)), block(256);
+  switch (nb) {
+#define CASE(N) \
+  case N: hipLaunchKernelGGL((k_conv_dgrad<STRIDE, TAPS, N>), grid, block, 0, s, dy, wt, dx, acc, g); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+  }
+}
+
+template <int STRIDE, int TAPS>
+static void launch_wgrad_tpw(int tpw, const uint16_t* x, const uint16_t* dy, float* partial,
+                             int64_t chunk, int64_t chunks, const Geom& g, hipStream_t s) {
+  const dim3 grid((unsigned)chunks, TAPS), block(256);
+  switch (tpw) {
+#define CASE(N) \
+  case N: hipLaunchKernelGGL((k_conv_wgrad<STRIDE, TAPS, N>), grid, block, 0, s, x, dy, partial, chunk, g); break;
+    CASE(1) CASE(2) CASE(4) CASE(8)
+#undef CASE
+  }
+}
+
+}  // namespace nn
+}  // namespace lbm
+
+using namespace lbm::nn;
+using lbm::set_error;
+
+#define NN_HIP_CHECK(what)                                                    \
+  do {                                                                        \
+    hipError_t e_ = hipGetLastError();                                        \
+    if (e_ != hipSuccess) {                                                   \
+      set_error("%s: %s", what, hipGetErrorString(e_));                       \
+      return -4;                                                              \
+    }                                                                         \
+  } while (0)
+
+extern "C" {
+
+int nn_conv3d_fwd(const nn_conv_desc* d, const uint16_t* x, const uint16_t* w, const float* bias,
+                  void* y, void* stream) {
+  if (check_desc(d)) return -1;
+  if (!x || !w || !y) { set_error("null tensor"); return -1; }
+  const Geom g = make_geom(d);
+  hipStream_t s = (hipStream_t)stream;
+  const int nb = d->c_out / 16;
+  if (d->taps == 1) {
+    if (d->stride != 1) { set_error("1x1x1 convolution has stride 1"); return -1; }
+    if (d->out_f32) launch_fwd_nb<1, 1, true>(nb, x, w, bias, y, g, s);
+    else launch_fwd_nb<1, 1, false>(nb, x, w, bias, y, g, s);
+  } else if (d->stride == 1) {
+    if (d->out_f32) launch_fwd_nb<1, 27, true>(nb, x, w, bias, y, g, s);
+    else launch_fwd_nb<1, 27, false>(nb, x, w, bias, y, g, s);
+  } else {
+    if (d->out_f32) launch_fwd_nb<2, 27, true>(nb, x, w, bias, y, g, s);
+    else launch_fwd_nb<2, 27, false>(nb, x, w, bias, y, g, s);
+  }
+  NN_HIP_CHECK("conv fwd");
+  return 0;
+}
+
+int nn_conv3d_dgrad(const nn_conv_desc* d, const uint16_t* dy, const uint16_t* w, uint16_t* w_t,
+                    float* dx, int32_t accumulate, void* stream) {
+  if (check_desc(d)) return -1;
+  if (!dy || !w || !w_t || !dx) { set_error("null tensor"); return -1; }
+  const Geom g = make_geom(d);
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nw = (int64_t)d->taps * d->c_out * d->c_in;
+  hipLaunchKernelGGL(k_transpose_w, dim3(nblk(nw, 256)), dim3(256), 0, s, w, w_t, d->taps, d->c_out,
+                     d->c_in);
+  const int nb = d->c_in / 16;
+  if (d->taps == 1) launch_dgrad_nb<1, 1>(nb, dy, w_t, dx, accumulate, g, s);
+  else if (d->stride == 1) launch_dgrad_nb<1, 27>(nb, dy, w_t, dx, accumulate, g, s);
+  else launch_dgrad_nb<2, 27>(nb, dy, w_t, dx, accumulate, g, s);
+  NN_HIP_CHECK("conv dgrad");
+  return 0;
+}
+
+int64_t nn_conv3d_wgrad_workspace(const nn_conv_desc* d) {
+  if (check_desc(d)) return -1;
+  const Geom g = make_geom(d);
+  int64_t chunks;
+  wgrad_chunk(g, &chunks);
+  return (chunks * d->taps * d->c_out * d->c_in + chunks * d->c_out) * (int64_t)sizeof(float);
+}
+
+int nn_conv3d_wgrad(const nn_conv_desc* d, const uint16_t* x, const uint16_t* dy, float* dw,
+                    float* db, float* workspace, void* stream) {
+  if (check_desc(d)) return -1;
+  if (!x || !dy || !dw || !workspace) { set_error("null tensor"); return -1; }
+  const Geom g = make_geom(d);
+  hipStream_t s = (hipStream_t)stream;
+  int64_t chunks;
+  const int64_t chunk = wgrad_chunk(g, &chunks);
+  const int ntiles = (d->c_out / 16) * (d->c_in / 16);
+  int tpw = (ntiles + 3) / 4;
+  tpw = tpw <= 1 ? 1 : (tpw <= 2 ? 2 : (tpw <= 4 ? 4 : 8));
+  if (d->taps == 1) launch_wgrad_tpw<1, 1>(tpw, x, dy, workspace, chunk, chunks, g, s);
+  else if (d->stride == 1) launch_wgrad_tpw<1, 27>(tpw, x, dy, workspace, chunk, chunks, g, s);
+  else launch_wgrad_tpw<2, 27>(tpw, x, dy, workspace, chunk, chunks, g, s);
+  const int64_t nw = (int64_t)d->taps * d->c_out * d->c_in;
+  hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(nw, 256)), dim3(256), 0, s, workspace, dw, nw, chunks);
+  if (db) {
+    float* bpart = workspace + chunks * nw;
+    hipLaunchKernelGGL(k_bias_partial, dim3((unsigned)chunks), dim3(256), 0, s, dy, bpart, chunk,
+                       g.m_out, d->c_out);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, s, bpart, db, (int64_t)d->c_out, chunks);
+  }
+  NN_HIP_CHECK("conv wgrad");
+  return 0;
+}
+
+int nn_lrelu_bwd(const float* dx, const uint16_t* y, uint16_t* dy_pre, int64_t n, float slope,
+                 void* stream) {
+  if (!dx || !y || !dy_pre || n < 0) { set_error("bad arguments"); return -1; }
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_lrelu_bwd, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, dx, y,
+                     dy_pre, n, slope);
+  NN_HIP_CHECK("lrelu bwd");
+  return 0;
+}
+
+int nn_up_concat(const uint16_t* coarse, const uint16_t* skip, uint16_t* cat, int32_t batch,
+                 int32_t d, int32_t h, int32_t w, int32_t c1, int32_t c2, void* stream) {
+  if (!coarse || !skip || !cat || batch < 1 || d % 2 || h % 2 || w % 2 || c1 < 1 || c2 < 1) {
+    set_error("bad arguments");
+    return -1;
+  }
+  const int64_t nvox = (int64_t)batch * d * h * w;
+  hipLaunchKernelGGL(k_up_concat, dim3(nblk(nvox * (c1 + c2), 256)), dim3(256), 0,
+                     (hipStream_t)stream, coarse, skip, cat, nvox, d, h, w, c1, c2);
+  NN_HIP_CHECK("up concat");
+  return 0;
+}
+
+int nn_split_down(const float* dcat, float* dcoarse, float* dskip, int32_t batch, int32_t d,
+                  int32_t h, int32_t w, int32_t c1, int32_t c2, void* stream) {
+  if (!dcat || !dcoarse || !dskip || batch < 1 || d % 2 || h % 2 || w % 2 || c1 < 1 || c2 < 1) {
+    set_error("bad arguments");
+    return -1;
+  }
+  const int64_t nfine = (int64_t)batch * d * h * w;
+  const int64_t ncoarse = nfine / 8;
+  hipLaunchKernelGGL(k_split_down_coarse, dim3(nblk(ncoarse * c1, 256)), dim3(256), 0,
+                     (hipStream_t)stream, dcat, dcoarse, ncoarse, d, h, w, c1, c2);
+  hipLaunchKernelGGL(k_split_down_skip, dim3(nblk(nfine * c2, 256)), dim3(256), 0,
+                     (hipStream_t)stream, dcat, dskip, nfine, c1, c2);
+  NN_HIP_CHECK("split down");
+  return 0;
+}
+
+int nn_masked_mse(const float* pred, const float* target, const uint8_t* mask, int64_t n,
+                  uint16_t* dy, float* loss, float* workspace, void* stream) {
+  if (!pred || !target || !mask || !dy || !loss || !workspace || n < 1) {
+    set_error("bad arguments");
+    return -1;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int nb = (int)((n + 255) / 256);
+  if (nb > 2046) nb = 2046;
+  hipLaunchKernelGGL(k_mse_partial, dim3(nb), dim3(256), 0, s, pred, target, mask, n, workspace);
+  float* count = workspace + 2 * 2046 + 1;
+  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, s, workspace, nb, loss, count);
+  hipLaunchKernelGGL(k_mse_grad, dim3(nblk(n * 16, 256)), dim3(256), 0, s, pred, target, mask, n,
+                     count, dy);
+  NN_HIP_CHECK("masked mse");
+  return 0;
+}
+
+int nn_adam_step(float* param, const float* grad, float* m, float* v, uint16_t* param_bf16,
+                 int64_t n, float lr, float beta1, float beta2, float eps, int32_t t,
+                 void* stream) {
+  if (!param || !grad || !m || !v || !param_bf16 || n < 1 || t < 1) {
+    set_error("bad arguments");
+    return -1;
+  }
+  const float c1 = 1.f - powf(beta1, (float)t), c2 = 1.f - powf(beta2, (float)t);
+  hipLaunchKernelGGL(k_adam, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, param, grad, m,
+                     v, param_bf16, n, lr, beta1, beta2, eps, c1, c2);
+  NN_HIP_CHECK("adam");
+  return 0;
+}
+
+int nn_prepare_input(const uint8_t* mask, uint16_t* x, int64_t n, int32_t c_pad, void* stream) {
+  if (!mask || !x || n < 1 || c_pad < 2) { set_error("bad arguments"); return -1; }
+  hipLaunchKernelGGL(k_prepare_input, dim3(nblk(n * c_pad, 256)), dim3(256), 0,
+                     (hipStream_t)stream, mask, x, n, c_pad);
+  NN_HIP_CHECK("prepare input");
+  return 0;
+}
+
+int nn_velocity_out(const float* pred, const uint8_t* mask, double scale, double* u, int64_t n,
+                    void* stream) {
+  if (!pred || !mask || !u || n < 1) { set_error("bad arguments"); return -1; }
+  hipLaunchKernelGGL(k_velocity_out, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, pred,
+                     mask, scale, u, n);
+  NN_HIP_CHECK("velocity out");
+  return 0;
+}
+
+int nn_to_bf16(const float* src, uint16_t* dst, int64_t n, void* stream) {
+  if (!src || !dst || n < 1) { set_error("bad arguments"); return -1; }
+  hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, src, dst, n);
+  NN_HIP_CHECK("to bf16");
+  return 0;
+}
+
+}  // extern "C"

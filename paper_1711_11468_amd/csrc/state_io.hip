@@ -114,11 +114,16 @@ struct CanonFromArray {
   __device__ double operator()(int64_t node, int i, const View&) const { return P[node * Q + i]; }
 };
 
+// The equilibrium is taken at u - g/(2 rho): the macroscopic velocity is
+// u = (sum c f + g/2)/rho, so this makes the state report exactly the
+// requested velocity (an equilibrium at u itself would carry an extra
+// momentum g/2 per node, which decays only slowly).
 struct CanonFromFields {
   const double* rho;  // N or null (1)
   const double* u;    // [3][N] or null (0)
   int64_t n_nodes;
   int fullway;
+  double gx, gy, gz;
   __device__ double operator()(int64_t node, int i, const View& v) const {
     if (fullway && v.mask[node] != 0) return weight(i);
     const double r = rho ? rho[node] : 1.0;
@@ -128,7 +133,8 @@ struct CanonFromFields {
       uy = u[n_nodes + node];
       uz = u[2 * n_nodes + node];
     }
-    return weight(i) + eq_shifted(i, r, ux, uy, uz);
+    const double h = 0.5 / r;
+    return weight(i) + eq_shifted(i, r, ux - h * gx, uy - h * gy, uz - h * gz);
   }
 };
 
@@ -171,7 +177,8 @@ hipError_t launch_init_fields(lbm_ctx* c, const double* rho_dev, const double* u
   return dispatch(c->p, [&](auto st, auto lay, auto addr, auto bb) -> hipError_t {
     using ST = decltype(st);
     const int64_t n = c->s.n_sites;
-    CanonFromFields P{rho_dev, u_dev, c->s.n_nodes, c->p.bounce == LBM_FULLWAY ? 1 : 0};
+    CanonFromFields P{rho_dev, u_dev, c->s.n_nodes, c->p.bounce == LBM_FULLWAY ? 1 : 0,
+                      c->p.g[0], c->p.g[1], c->p.g[2]};
     hipLaunchKernelGGL((k_scatter_canonical<ST, decltype(lay)::value, decltype(addr)::value,
                                             decltype(bb)::value, CanonFromFields>),
                        dim3(grid_for(n, 256)), dim3(256), 0, c->stream, P, make_view(c), n,

@@ -21,7 +21,7 @@ def _declared():
         if fn.endswith(".h"):
             txt = open(os.path.join(ROOT, "include", fn)).read()
             txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-            names |= set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", txt))
+            names |= set(re.findall(r"\b((?:lbm|nn)_[a-z0-9_]+)\s*\(", txt))
     return names
 
 
@@ -31,7 +31,8 @@ def test_library_exports_every_declared_symbol():
     assert {"lbm_plan", "lbm_init_geometry", "lbm_step", "lbm_macroscopic", "lbm_verify"} <= declared
     for name in declared:
         assert hasattr(lib, name), name
-    assert set(lbm.EXPORTED) == declared
+    from paper_1711_11468_amd import nn
+    assert set(lbm.EXPORTED) | set(nn.NN_EXPORTED) == declared
 
 
 def test_plan_sizes_channel():

@@ -212,3 +212,26 @@ def test_nonfinite_detected(L):
     lat.import_(f)
     st = lat.macroscopic(allow_nonfinite=True)
     assert st["rc"] == L.ENONFINITE and st["nonfinite"] >= 1
+
+
+@pytest.mark.parametrize("kw", [{"addressing": "list", "bounce": "halfway"},
+                                {"layout": "aos", "bounce": "fullway"},
+                                {"storage": "f32s"}])
+def test_init_fields_reports_given_state(L, kw):
+    """After lbm_init_fields(rho, u) the diagnostics report exactly that
+    density and velocity on fluid nodes (the equilibrium is taken at
+    u - g/(2 rho) because the velocity includes half the force)."""
+    import torch
+    mask = I.random_solid_mask(16, 12, 10, seed=11, fraction=0.2)
+    n = mask.size
+    rng = np.random.default_rng(3)
+    rho = 1.0 + 1e-3 * rng.uniform(-1, 1, n)
+    u = 1e-3 * rng.uniform(-1, 1, (3, n))
+    lat = L.Lattice(mask, g=(2e-4, -1e-4, 5e-5), **kw)
+    dev = lat.device
+    lat.init_fields(torch.from_numpy(rho).to(dev), torch.from_numpy(u.reshape(-1)).to(dev))
+    st = lat.macroscopic(fields=True)
+    fl = mask.reshape(-1) == 0
+    tol = 1e-15 if kw.get("storage", "f64") == "f64" else 1e-9
+    np.testing.assert_allclose(st["rho"].cpu().numpy()[fl], rho[fl], rtol=0, atol=tol * 1e2)
+    np.testing.assert_allclose(st["u"].cpu().numpy()[:, fl], u[:, fl], rtol=0, atol=tol)
