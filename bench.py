@@ -137,6 +137,28 @@ def warm_vs_cold(n=128, seeds=(100000, 100001, 100002)):
             "prediction_rel_l2_median": float(np.median([r["prediction_rel_l2"] for r in rows]))}
 
 
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel), or None
+    when the sweep sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sweep_soa_f64_channel512_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_sha256_16"):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip()
+    h = hashlib.sha256()
+    for f in ("paper_1711_11468_amd/csrc/sweep.hip", "paper_1711_11468_amd/csrc/d3q19.hpp"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != vals.get("source_sha256_16"):
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def cpu_baseline():
     """The oracle (single-threaded C, as it stands) on a bounded sample of
     the headline workload: a 16-node-long section of the same 512 x 512
@@ -189,6 +211,7 @@ def main():
         for name, kw in [("aos_f64", dict(layout="aos")),
                          ("soa_f32_shifted", dict(storage="f32s")),
                          ("soa_f16_shifted", dict(storage="f16s")),
+                         ("soa_f16_shifted_stochastic", dict(storage="f16sr")),
                          ("soa_f64_halfway", dict(bounce="halfway"))]:
             log("variant %s" % name)
             lat, r = run_variant(mask, args.steps, args.warmup, **kw)
@@ -208,6 +231,7 @@ def main():
     steady = None if args.headline_only else warm_vs_cold()
     cpu = None if args.no_cpu else cpu_baseline()
     achieved = head["achieved_gbs"]
+    traffic = measured_traffic() if n == 512 else None
     line = {
         "metric": METRIC,
         "value": round(head["mflups"], 1),
@@ -227,7 +251,8 @@ def main():
                    "nodes": n ** 3, "fluid_nodes": head["n_fluid"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
+                     "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_sweep_direct<StoreF64, SOA, FULLWAY>",
                      "algorithmic_bytes_per_launch": head["bytes_per_update"] * head["n_sites"],
                      "kernel_ms": round(head["kernel_ms"], 4),
