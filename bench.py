@@ -212,7 +212,8 @@ def main():
                          ("soa_f32_shifted", dict(storage="f32s")),
                          ("soa_f16_shifted", dict(storage="f16s")),
                          ("soa_f16_shifted_stochastic", dict(storage="f16sr")),
-                         ("soa_f64_halfway", dict(bounce="halfway"))]:
+                         ("soa_f64_halfway", dict(bounce="halfway")),
+                         ("aa_soa_f64", dict(propagation="aa"))]:
             log("variant %s" % name)
             lat, r = run_variant(mask, args.steps, args.warmup, **kw)
             variants[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
@@ -221,6 +222,8 @@ def main():
         log("variant list 384^3 spheres")
         smask, phi, _ = I.spheres_mask(384, 384, 384, seed=0, porosity=0.4, rmin=8, rmax=16)
         for name, kw in [("list_spheres384_f64", dict(addressing="list", bounce="halfway")),
+                         ("aa_list_spheres384_f64", dict(addressing="list", bounce="halfway",
+                                                         propagation="aa")),
                          ("direct_spheres384_f64", dict(addressing="direct", bounce="halfway"))]:
             lat, r = run_variant(smask, args.steps, args.warmup, **kw)
             r["porosity"] = phi

@@ -82,6 +82,11 @@ extern "C" {
                                 expected stored value is exact, so updates
                                 smaller than half an ulp are not lost      */
 
+#define LBM_OS 0             /* one step, two lattices A -> B (Sect. 3)    */
+#define LBM_AA 1             /* AA pattern, one lattice updated in place:
+                                alternating node-local (even) and
+                                neighbour (odd) kernels (Sect. 3)          */
+
 #define LBM_FULLWAY 0        /* solids store and reverse populations       */
 #define LBM_HALFWAY 1        /* mid-link reflection in the same step       */
 
@@ -105,6 +110,8 @@ typedef struct {
   int32_t cu_slots;         /* at most this many sweep workgroups per
                                compute unit (reserved LDS caps residency);
                                0 = no cap                                  */
+  int32_t propagation;      /* LBM_OS | LBM_AA (AA: SOA layout; pdf_b is
+                               not used and may be NULL)                   */
   double tau_plus;          /* > 1/2; kinematic viscosity (tau+ - 1/2)/3   */
   double magic_lambda;      /* Lambda > 0                                  */
   double g[3];              /* body-force density, lattice units           */
@@ -129,7 +136,7 @@ typedef struct {
 
 typedef struct {            /* device pointers, caller-owned               */
   void* pdf_a;              /* pdf_bytes, 256-byte aligned                 */
-  void* pdf_b;              /* pdf_bytes, 256-byte aligned                 */
+  void* pdf_b;              /* pdf_bytes, 256-byte aligned (LBM_OS only)   */
   uint8_t* mask;            /* mask_bytes                                  */
   int32_t* adj;             /* LIST only, else NULL                        */
   int32_t* fluid_index;     /* LIST only, else NULL                        */
@@ -193,9 +200,14 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params,
  * the step counter and the residual history.  Errors: EINVAL, EDEVICE. */
 int lbm_init_fields(lbm_ctx* ctx, const double* rho_dev, const double* u_dev);
 
-/* Enqueue n fused stream-collide updates (one kernel launch each, source
- * and destination buffers swap after every launch; Sect. 3 "One Step
- * Kernels").  Asynchronous.  Errors: EINVAL (n < 0), EDEVICE. */
+/* Enqueue n fused stream-collide updates, one kernel launch each.
+ * LBM_OS: source and destination buffers swap after every launch (Sect. 3
+ * "One Step Kernels").  LBM_AA: one buffer; launches alternate between the
+ * node-local kernel (read a node's populations, collide, write them back
+ * reversed) and the neighbour kernel (read each population from the slot
+ * the previous local step left it in at the neighbour, collide, write it
+ * where the next local step expects it), Sect. 3 "AA Pattern Kernels".
+ * Asynchronous.  Errors: EINVAL (n < 0), EDEVICE. */
 int lbm_step(lbm_ctx* ctx, int32_t n);
 
 /* Macroscopic fields and diagnostics of the current state.  rho_dev (N

@@ -101,15 +101,26 @@ struct StoreF16ShiftedSR {
   static constexpr bool kShifted = true;
   static constexpr bool kStochastic = true;
   __device__ __forceinline__ static R load(T v, R inv_scale) { return (R)v * inv_scale; }
-  __device__ __forceinline__ static T store(R v, R scale, uint32_t key) {
-    return f32_to_f16_stochastic(v * scale, mix32(key));
+  // rnd: 13 uniformly distributed random bits in the low bits
+  __device__ __forceinline__ static T store(R v, R scale, uint32_t rnd) {
+    return f32_to_f16_stochastic(v * scale, rnd);
   }
 };
 
-// Random key of the value stored for (node n, direction i) at time step t.
-__device__ __forceinline__ uint32_t sr_key(uint32_t n, int i, uint32_t t) {
-  return mix32(n * 0x9E3779B1u + (uint32_t)i) ^ (t * 0x85ebca77u + 0x165667b1u);
-}
+// Random bits for stochastic rounding.  One hash per (node, time step):
+// mix32 of the node index xor a hash of the step; the 19 values of the node
+// then take successive states of a 32-bit linear congruential generator
+// (Numerical Recipes constants) seeded with it, using its top 13 bits (the
+// well-mixed ones).  Deterministic: a function of (node, direction, step).
+struct SrStream {
+  uint32_t s;
+  __device__ __forceinline__ SrStream(uint32_t node, uint32_t step, bool on)
+      : s(on ? mix32(node * 0x9E3779B1u ^ mix32(step * 0x85ebca77u + 0x165667b1u)) : 0u) {}
+  __device__ __forceinline__ uint32_t next() {
+    s = s * 1664525u + 1013904223u;
+    return s >> 19;
+  }
+};
 
 // Collision constants in the arithmetic type.
 template <typename R>

@@ -20,6 +20,10 @@ struct View {
   const int32_t* node_map;
   const int32_t* fluid_index;
   float scale, inv_scale;  // half-precision storage scale (else 1)
+  int aa;                  // 0: two-lattice pull buffer; 1: AA lattice after an
+                           // even number of updates (canonical in place);
+                           // 2: AA lattice after an odd number (post-collision,
+                           // stored reversed at the node)
 };
 
 template <int LAYOUT>
@@ -71,18 +75,29 @@ __device__ __forceinline__ bool gather_canonical(const typename ST::T* __restric
     if (m < 0) return false;
     f[0] = to_f64<ST>(src[m], 0, v);
 #pragma unroll
-    for (int i = 1; i < Q; ++i) f[i] = to_f64<ST>(src[v.adj[(int64_t)(i - 1) * v.stride + m]], i, v);
+    for (int i = 1; i < Q; ++i) {
+      const int64_t at = v.aa == 1 ? (int64_t)i * v.stride + m : (int64_t)v.adj[(int64_t)(i - 1) * v.stride + m];
+      f[i] = to_f64<ST>(src[at], i, v);
+    }
     return true;
   }
   const bool solid = v.mask[node] != 0;
   if (BB == LBM_HALFWAY && solid) return false;
+  if (v.aa == 1) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = to_f64<ST>(src[vslot<LAYOUT>(node, i, v.stride)], i, v);
+    return true;
+  }
   int x, y, z;
   node_xyz(v, node, x, y, z);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int64_t sn = wrap_node(v, x - Vel::cx[i], y - Vel::cy[i], z - Vel::cz[i]);
-    int64_t at = vslot<LAYOUT>(sn, i, v.stride);
-    if (BB == LBM_HALFWAY && i != 0 && v.mask[sn] != 0) at = vslot<LAYOUT>(node, Vel::opp[i], v.stride);
+    // two-lattice pull buffer: slot i of the neighbour; AA after an odd
+    // number of updates: slot opp(i) of the neighbour (stored reversed)
+    int64_t at = vslot<LAYOUT>(sn, v.aa == 2 ? Vel::opp[i] : i, v.stride);
+    if (BB == LBM_HALFWAY && i != 0 && v.mask[sn] != 0)
+      at = vslot<LAYOUT>(node, v.aa == 2 ? i : Vel::opp[i], v.stride);
     f[i] = to_f64<ST>(src[at], i, v);
   }
   return true;

@@ -13,6 +13,7 @@ struct lbm_ctx {
   lbm_buffers b;
   hipStream_t stream;
   int cur;             // index of the buffer holding the current state
+  int aa_odd;          // AA: the next launch is the neighbour kernel
   int64_t step;        // updates since init
   int u_prev_valid;    // u_prev holds the velocity of a previous call
   int block;           // threads per workgroup for the sweeps

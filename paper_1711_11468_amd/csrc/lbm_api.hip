@@ -65,6 +65,11 @@ static int validate(const lbm_params* p) {
   }
   if (p->pad < -1 || p->pad > (1 << 24)) { set_error("pad must be -1 or in [0, 2^24]"); return LBM_EINVAL; }
   if (p->cu_slots < 0 || p->cu_slots > 64) { set_error("cu_slots must be in [0, 64]"); return LBM_EINVAL; }
+  if (p->propagation != LBM_OS && p->propagation != LBM_AA) { set_error("bad propagation"); return LBM_EINVAL; }
+  if (p->propagation == LBM_AA && p->layout != LBM_SOA) {
+    set_error("the AA pattern is implemented for the SOA layout");
+    return LBM_EINVAL;
+  }
   for (int a = 0; a < 3; ++a)
     if (!(p->g[a] == p->g[a]) || p->g[a] > 1e30 || p->g[a] < -1e30) { set_error("bad g"); return LBM_EINVAL; }
   return LBM_OK;
@@ -110,8 +115,11 @@ static int plan_sizes(const lbm_params* p, int64_t n_fluid, lbm_sizes* s) {
   // Algorithmic HBM bytes per site update: 19 loads + 19 stores of one
   // element, plus the flag byte (direct, full-way), the link word (direct,
   // half-way) or 18 int32 adjacency entries (list).
+  // The AA pattern on the list reads the adjacency in the neighbour kernel
+  // only: 18*4 B every other update (Table 1: 340 B/FLUP in FP64).
+  const double adj_bytes = p->propagation == LBM_AA ? 2.0 * (Q - 1) : 4.0 * (Q - 1);
   s->bytes_per_update =
-      2.0 * Q * es + (p->addressing == LBM_LIST ? 4.0 * (Q - 1) : (links ? 4.0 : 1.0));
+      2.0 * Q * es + (p->addressing == LBM_LIST ? adj_bytes : (links ? 4.0 : 1.0));
   return LBM_OK;
 }
 
@@ -166,11 +174,12 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
   if (N >= 0x7fffffffLL) { set_error("lattice too large"); return LBM_EOVERFLOW; }
   rc = plan_sizes(params, count_fluid(params, mask_host), &s);
   if (rc) return rc;
-  if (!bufs->pdf_a || !bufs->pdf_b || !bufs->mask || !bufs->scratch) {
-    set_error("pdf_a, pdf_b, mask and scratch are required");
+  const bool two = params->propagation == LBM_OS;
+  if (!bufs->pdf_a || (two && !bufs->pdf_b) || !bufs->mask || !bufs->scratch) {
+    set_error("pdf_a, pdf_b (one-step propagation), mask and scratch are required");
     return LBM_EINVAL;
   }
-  if (!aligned256(bufs->pdf_a) || !aligned256(bufs->pdf_b)) {
+  if (!aligned256(bufs->pdf_a) || (two && !aligned256(bufs->pdf_b))) {
     set_error("pdf buffers must be 256-byte aligned");
     return LBM_EINVAL;
   }
@@ -195,11 +204,13 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
   if (s.links_bytes == 0) c->b.links = nullptr;
   c->stream = (hipStream_t)stream;
   c->cur = 0;
+  c->aa_odd = 0;
   c->step = 0;
   c->u_prev_valid = 0;
   // 512 threads: one workgroup covers a 512-node row in one pass, which
-  // measured fastest for the direct sweeps; the list sweep likes it too.
-  c->block = params->block ? params->block : 512;
+  // measured fastest for the one-step sweeps (the list sweep likes it too);
+  // the in-place AA kernels measured faster with 256.
+  c->block = params->block ? params->block : (params->propagation == LBM_AA ? 256 : 512);
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) { delete c; return hip_fail(e, "hipGetDevice"); }
 
@@ -246,8 +257,12 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
   }
   e = launch_fill_rest(c, c->b.pdf_a);
   if (e != hipSuccess) return fail(e, "rest fill A");
-  e = launch_fill_rest(c, c->b.pdf_b);
-  if (e != hipSuccess) return fail(e, "rest fill B");
+  if (two) {
+    e = launch_fill_rest(c, c->b.pdf_b);
+    if (e != hipSuccess) return fail(e, "rest fill B");
+  } else {
+    c->b.pdf_b = nullptr;
+  }
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return fail(e, "init sync");
   *out = c;
@@ -257,6 +272,7 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
 int lbm_init_fields(lbm_ctx* c, const double* rho_dev, const double* u_dev) {
   if (!c) { set_error("ctx is NULL"); return LBM_EINVAL; }
   LBM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  c->aa_odd = 0;  // AA: equilibrium written in place (even phase)
   LBM_HIP(launch_init_fields(c, rho_dev, u_dev, pdf_buf(c, c->cur)), "init fields kernel");
   LBM_HIP(hipStreamSynchronize(c->stream), "init fields sync");
   c->step = 0;
@@ -268,9 +284,15 @@ int lbm_step(lbm_ctx* c, int32_t n) {
   if (!c || n < 0) { set_error("bad ctx or negative step count"); return LBM_EINVAL; }
   LBM_HIP(hipSetDevice(c->device), "hipSetDevice");
   for (int32_t k = 0; k < n; ++k) {
-    hipError_t e = launch_sweep(c, pdf_buf(c, c->cur), pdf_buf(c, 1 - c->cur));
-    if (e != hipSuccess) return hip_fail(e, "sweep launch");
-    c->cur = 1 - c->cur;
+    if (c->p.propagation == LBM_AA) {
+      hipError_t e = launch_sweep(c, pdf_buf(c, 0), nullptr);
+      if (e != hipSuccess) return hip_fail(e, "AA sweep launch");
+      c->aa_odd = 1 - c->aa_odd;
+    } else {
+      hipError_t e = launch_sweep(c, pdf_buf(c, c->cur), pdf_buf(c, 1 - c->cur));
+      if (e != hipSuccess) return hip_fail(e, "sweep launch");
+      c->cur = 1 - c->cur;
+    }
     c->step += 1;
   }
   return LBM_OK;
@@ -391,6 +413,7 @@ int lbm_import_pdfs(lbm_ctx* c, const double* host_in) {
     return LBM_ENOMEM;
   }
   hipError_t e = hipMemcpyAsync(canon, host_in, bytes, hipMemcpyHostToDevice, c->stream);
+  c->aa_odd = 0;  // AA: the canonical state is written in place (even phase)
   if (e == hipSuccess) e = launch_import(c, canon, pdf_buf(c, c->cur));
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipFree(canon);

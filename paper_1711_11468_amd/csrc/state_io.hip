@@ -16,6 +16,7 @@ static View make_view(const lbm_ctx* c) {
   v.adj = c->b.adj;
   v.node_map = c->b.node_map;
   v.fluid_index = c->b.fluid_index;
+  v.aa = c->p.propagation == LBM_AA ? (c->aa_odd ? 2 : 1) : 0;
   if (c->p.storage == LBM_F16_SHIFTED || c->p.storage == LBM_F16_SHIFTED_SR) {
     v.scale = ldexpf(1.0f, c->p.f16_scale_log2);
     v.inv_scale = ldexpf(1.0f, -c->p.f16_scale_log2);
@@ -56,7 +57,9 @@ hipError_t launch_fill_rest(lbm_ctx* c, void* buf) {
 // adj[(i-1)*stride + m] = slot a pull of direction i reads for list node m:
 // the neighbour's slot i*stride + map(x - c_i), or the node's own opposite
 // slot opp(i)*stride + m when the neighbour is solid (half-way bounce-back).
-__global__ void k_build_adjacency(View v, int nf, int32_t* __restrict__ adj) {
+// For the AA pattern the neighbour kernel reads the reversed slots instead:
+// opp(i)*stride + map(x - c_i), or i*stride + m at a solid neighbour.
+__global__ void k_build_adjacency(View v, int nf, int aa, int32_t* __restrict__ adj) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= nf) return;
   int x, y, z;
@@ -65,7 +68,9 @@ __global__ void k_build_adjacency(View v, int nf, int32_t* __restrict__ adj) {
   for (int i = 1; i < Q; ++i) {
     const int64_t sn = wrap_node(v, x - Vel::cx[i], y - Vel::cy[i], z - Vel::cz[i]);
     const int t = v.node_map[sn];
-    const int64_t s = t >= 0 ? (int64_t)i * v.stride + t : (int64_t)Vel::opp[i] * v.stride + m;
+    const int dn = aa ? Vel::opp[i] : i;     // direction slot at the neighbour
+    const int ds = aa ? i : Vel::opp[i];     // direction slot at the node itself
+    const int64_t s = t >= 0 ? (int64_t)dn * v.stride + t : (int64_t)ds * v.stride + m;
     adj[(int64_t)(i - 1) * v.stride + m] = (int32_t)s;
   }
 }
@@ -74,7 +79,7 @@ hipError_t launch_build_adjacency(lbm_ctx* c) {
   const int nf = (int)c->s.n_fluid;
   if (nf == 0) return hipSuccess;
   hipLaunchKernelGGL(k_build_adjacency, dim3(grid_for(nf, 256)), dim3(256), 0, c->stream,
-                     make_view(c), nf, c->b.adj);
+                     make_view(c), nf, c->p.propagation == LBM_AA ? 1 : 0, c->b.adj);
   return hipGetLastError();
 }
 
@@ -147,6 +152,12 @@ __global__ void k_scatter_canonical(SRC P, View v, int64_t n_sites, typename ST:
   if (ADDR == LBM_DIRECT && BB == LBM_HALFWAY && v.mask[node] != 0) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) dst[vslot<LAYOUT>(site, i, v.stride)] = rest_value<ST>(i);
+    return;
+  }
+  if (v.aa) {
+    // AA lattice: the canonical state is stored in place (even phase)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dst[vslot<LAYOUT>(site, i, v.stride)] = from_f64<ST>(P(node, i, v), i, v);
     return;
   }
   int x, y, z;

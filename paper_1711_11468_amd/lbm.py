@@ -21,6 +21,7 @@ SOA, AOS = 0, 1
 DIRECT, LIST = 0, 1
 F64, F32_SHIFTED, F16_SHIFTED, F16_SHIFTED_SR = 0, 1, 2, 3
 FULLWAY, HALFWAY = 0, 1
+OS, AA = 0, 1
 VERIFY_SLAB, VERIFY_DUCT, VERIFY_REFERENCE = 0, 1, 2
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, ENONFINITE, ENOTCONV = 0, -1, -2, -3, -4, -5, -6
 
@@ -28,6 +29,7 @@ _LAYOUTS = {"soa": SOA, "aos": AOS}
 _ADDR = {"direct": DIRECT, "list": LIST}
 _STORAGE = {"f64": F64, "f32s": F32_SHIFTED, "f16s": F16_SHIFTED, "f16sr": F16_SHIFTED_SR}
 _BOUNCE = {"fullway": FULLWAY, "halfway": HALFWAY}
+_PROP = {"os": OS, "aa": AA}
 ELEM_BYTES = {F64: 8, F32_SHIFTED: 4, F16_SHIFTED: 2, F16_SHIFTED_SR: 2}
 
 
@@ -37,7 +39,7 @@ class Params(ctypes.Structure):
                 ("storage", ctypes.c_int32), ("bounce", ctypes.c_int32),
                 ("f16_scale_log2", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("cu_slots", ctypes.c_int32),
-                ("tau_plus", ctypes.c_double),
+                ("propagation", ctypes.c_int32), ("tau_plus", ctypes.c_double),
                 ("magic_lambda", ctypes.c_double), ("g", ctypes.c_double * 3)]
 
 
@@ -96,6 +98,13 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError("HIP library %s is missing: build it with "
                            "`python -m paper_1711_11468_amd.build`" % path)
+    # PyTorch ships its own HIP runtime under the same soname as the system
+    # one; importing it first makes the library bind to that single runtime
+    # (loading the system runtime first would leave two in the process).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P = ctypes.POINTER
     vp = ctypes.c_void_p
@@ -134,7 +143,7 @@ def _check(code, where):
 
 def make_params(shape, tau_plus=0.8, magic=3.0 / 16.0, g=(0.0, 0.0, 0.0), layout="soa",
                 addressing="direct", storage="f64", bounce="fullway", f16_scale_log2=14,
-                block=0, pad=-1, cu_slots=0) -> Params:
+                block=0, pad=-1, cu_slots=0, propagation="os") -> Params:
     nz, ny, nx = shape
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
@@ -146,6 +155,7 @@ def make_params(shape, tau_plus=0.8, magic=3.0 / 16.0, g=(0.0, 0.0, 0.0), layout
     p.block = block
     p.pad = pad
     p.cu_slots = cu_slots
+    p.propagation = _PROP[propagation]
     p.tau_plus = tau_plus
     p.magic_lambda = magic
     p.g[0], p.g[1], p.g[2] = (float(v) for v in g)
@@ -189,10 +199,10 @@ class Lattice:
             n = max(int(nbytes), 256)
             return torch.empty(n, dtype=torch.uint8, device=self.device)
 
-        self._t = {
-            "pdf_a": alloc(s.pdf_bytes), "pdf_b": alloc(s.pdf_bytes),
-            "mask": alloc(s.mask_bytes), "scratch": alloc(s.scratch_bytes),
-        }
+        self._t = {"pdf_a": alloc(s.pdf_bytes), "mask": alloc(s.mask_bytes),
+                   "scratch": alloc(s.scratch_bytes)}
+        if self.params.propagation == OS:
+            self._t["pdf_b"] = alloc(s.pdf_bytes)
         if self.params.addressing == LIST:
             self._t["adj"] = alloc(s.adj_bytes)
             self._t["fluid_index"] = alloc(s.fluid_index_bytes)
