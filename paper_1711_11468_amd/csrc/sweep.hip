@@ -80,59 +80,65 @@ k_sweep_soa(const typename ST::T* __restrict__ src, typename ST::T* __restrict__
   }
 }
 
-// The 9 source rows of a pull, as (c_y, c_z) of the directions they supply.
-struct SrcRows {
-  static constexpr int cy[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
-  static constexpr int cz[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
-};
-
+// AoS tile kernel.  A workgroup owns TY consecutive rows (y0 .. y0+TY-1) of
+// one z-layer and walks them in x-segments of BX nodes.  The pull sources of
+// that tile are the rows y0-1 .. y0+TY of the layers z, z-1 and z+1; each is
+// staged once, whole records, into LDS with contiguous loads, and every
+// thread takes from it the directions whose source it is for its own row
+// (a staged row supplies up to three output rows).  Results leave through
+// LDS again, one output row at a time, as contiguous runs of records.
 template <class ST, int BB>
 __global__ void __launch_bounds__(1024)
 k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
             const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx,
-            int ny, int nz, Collide<typename ST::R> k) {
+            int ny, int nz, int BX, Collide<typename ST::R> k) {
   using T = typename ST::T;
   using R = typename ST::R;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* sm = reinterpret_cast<T*>(lds_raw);
-  const int row = blockIdx.x;
-  const int y = row % ny;
-  const int z = row / ny;
-  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
-  const int B = blockDim.x;
-  const int t = threadIdx.x;
-  for (int x0 = 0; x0 < nx; x0 += B) {
-    const int seg = nx - x0 < B ? nx - x0 : B;
-    const bool active = t < seg;
-    const int x = x0 + t;
+  const int TY = blockDim.x / BX;
+  const int t = threadIdx.x, tx = t % BX, ty = t / BX;
+  const int tiles_y = (ny + TY - 1) / TY;
+  const int z = blockIdx.x / tiles_y;
+  const int y0 = (blockIdx.x - z * tiles_y) * TY;
+  const int y = y0 + ty;
+  for (int x0 = 0; x0 < nx; x0 += BX) {
+    const int seg = nx - x0 < BX ? nx - x0 : BX;
+    const bool active = y < ny && tx < seg;
     R f[Q];
 #pragma unroll
-    for (int r = 0; r < 9; ++r) {
-      const int dy = SrcRows::cy[r], dz = SrcRows::cz[r];
-      const int sy = dy == 1 ? ym : (dy == -1 ? yp : y);
-      const int sz = dz == 1 ? zm : (dz == -1 ? zp : z);
-      const int64_t rbase = (int64_t)(sy + ny * sz) * nx;
-      const int nrec = seg + 2;  // records x0-1 .. x0+seg of the source row
-      __syncthreads();
-      for (int e = t; e < nrec * Q; e += B) {
-        const int rr = e / Q;
-        const int i = e - rr * Q;
-        int xs = x0 - 1 + rr;
-        xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-        sm[e] = src[(rbase + xs) * Q + i];
-      }
-      __syncthreads();
-      if (active) {
+    for (int i = 0; i < Q; ++i) f[i] = R(0);
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-          if (Vel::cy[i] == dy && Vel::cz[i] == dz)
-            f[i] = ST::load(sm[(t + 1 - Vel::cx[i]) * Q + i], k.inv_scale);
+    for (int zz = 0; zz < 3; ++zz) {
+      const int dz = zz == 0 ? 0 : (zz == 1 ? 1 : -1);  // c_z supplied by this layer
+      int sz = z - dz;
+      sz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
+      for (int sr = -1; sr <= TY; ++sr) {
+        const int sy = ((y0 + sr) % ny + ny) % ny;
+        const int64_t rbase = ((int64_t)sy + (int64_t)ny * sz) * nx;
+        const int nrec = seg + 2;  // records x0-1 .. x0+seg
+        __syncthreads();
+        for (int e = t; e < nrec * Q; e += blockDim.x) {
+          const int rr = e / Q;
+          const int i = e - rr * Q;
+          int xs = x0 - 1 + rr;
+          xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+          sm[e] = src[(rbase + xs) * Q + i];
+        }
+        __syncthreads();
+        if (active) {
+          const int cy_req = ty - sr;  // y - c_y = y0 + sr
+#pragma unroll
+          for (int i = 0; i < Q; ++i) {
+            if (Vel::cz[i] != dz) continue;
+            if (Vel::cy[i] == cy_req) f[i] = ST::load(sm[(tx + 1 - Vel::cx[i]) * Q + i], k.inv_scale);
+          }
+        }
       }
     }
-    const int64_t n = (int64_t)row * nx + x;
-    bool solid = false;
+    const int64_t n = ((int64_t)y + (int64_t)ny * z) * nx + x0 + tx;
     if (active) {
+      bool solid;
       if (BB == LBM_HALFWAY) {
         const uint32_t lk = links[n];
         solid = (lk & 1u) != 0;
@@ -158,15 +164,19 @@ k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__
         for (int i = 0; i < Q; ++i) f[i] = ST::kShifted ? R(0) : R(weight(i));
       }
     }
-    __syncthreads();
-    if (active) {
-      SrStream rs((uint32_t)n, k.step, ST::kStochastic);
+    for (int w = 0; w < TY; ++w) {
+      __syncthreads();
+      if (active && ty == w) {
+        SrStream rs((uint32_t)n, k.step, ST::kStochastic);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) sm[t * Q + i] = ST::store(f[i], k.scale, rs.next());
+        for (int i = 0; i < Q; ++i) sm[tx * Q + i] = ST::store(f[i], k.scale, rs.next());
+      }
+      __syncthreads();
+      if (y0 + w < ny) {
+        T* out = dst + (((int64_t)(y0 + w) + (int64_t)ny * z) * nx + x0) * Q;
+        for (int e = t; e < seg * Q; e += blockDim.x) __builtin_nontemporal_store(sm[e], &out[e]);
+      }
     }
-    __syncthreads();
-    T* out = dst + ((int64_t)row * nx + x0) * Q;
-    for (int e = t; e < seg * Q; e += B) __builtin_nontemporal_store(sm[e], &out[e]);
   }
 }
 
@@ -345,9 +355,9 @@ static size_t sweep_lds(const lbm_ctx* c, size_t need) {
   return need;
 }
 
-size_t aos_lds_bytes(const lbm_ctx* c, int blk) {
+size_t aos_lds_bytes(const lbm_ctx* c, int bx) {
   const int es = c->p.storage == LBM_F64 ? 8 : (c->p.storage == LBM_F32_SHIFTED ? 4 : 2);  // F16: 2
-  return (size_t)(blk + 2) * Q * es;
+  return (size_t)(bx + 2) * Q * es;
 }
 
 template <class ST>
@@ -409,13 +419,20 @@ static hipError_t sweep_typed(lbm_ctx* c, const void* src, void* dst) {
       hipLaunchKernelGGL((k_sweep_soa<ST, LBM_HALFWAY>), grid, block, lds, c->stream, s, d,
                          c->b.mask, c->b.links, p.nx, p.ny, p.nz, c->s.stride, k);
   } else {
-    const size_t lds = sweep_lds(c, aos_lds_bytes(c, blk));
+    // tiles of TY rows x BX nodes: BX = min(128, nx rounded to 64), TY =
+    // workgroup size / BX
+    int bx = nx_r < 128 ? nx_r : 128;
+    int wg = c->block < bx ? bx : c->block;
+    wg = wg / bx * bx;
+    const int ty = wg / bx;
+    const dim3 tgrid((unsigned)((p.ny + ty - 1) / ty) * (unsigned)p.nz), tblock(wg);
+    const size_t lds = sweep_lds(c, aos_lds_bytes(c, bx));
     if (p.bounce == LBM_FULLWAY)
-      hipLaunchKernelGGL((k_sweep_aos<ST, LBM_FULLWAY>), grid, block, lds, c->stream, s, d,
-                         c->b.mask, c->b.links, p.nx, p.ny, p.nz, k);
+      hipLaunchKernelGGL((k_sweep_aos<ST, LBM_FULLWAY>), tgrid, tblock, lds, c->stream, s, d,
+                         c->b.mask, c->b.links, p.nx, p.ny, p.nz, bx, k);
     else
-      hipLaunchKernelGGL((k_sweep_aos<ST, LBM_HALFWAY>), grid, block, lds, c->stream, s, d,
-                         c->b.mask, c->b.links, p.nx, p.ny, p.nz, k);
+      hipLaunchKernelGGL((k_sweep_aos<ST, LBM_HALFWAY>), tgrid, tblock, lds, c->stream, s, d,
+                         c->b.mask, c->b.links, p.nx, p.ny, p.nz, bx, k);
   }
   return hipGetLastError();
 }

@@ -98,3 +98,27 @@ def test_null_arguments_rejected():
     assert lib.lbm_plan(None, None, None) == lbm.EINVAL
     assert lib.lbm_step_count(None) == -1
     assert lib.lbm_strerror(lbm.ENONFINITE) == b"non-finite populations"
+
+
+def test_plan_list_adjacency_overflow():
+    """A fluid list whose 19 direction arrays exceed 2^31 slots is refused
+    (the adjacency stores int32 slot indices)."""
+    m = np.zeros((115, 1024, 1000), dtype=np.uint8)  # 117.8 M fluid nodes
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.plan(m, addressing="list", bounce="halfway")
+    assert e.value.code == lbm.EOVERFLOW
+    s = lbm.plan(m)  # the full array itself is fine
+    assert s.n_nodes == m.size
+
+
+def test_plan_degenerate_geometries():
+    all_solid = np.ones((3, 4, 5), dtype=np.uint8)
+    s = lbm.plan(all_solid, addressing="list", bounce="halfway")
+    assert s.n_fluid == 0 and s.n_sites == 0
+    one = np.zeros((1, 1, 1), dtype=np.uint8)
+    s = lbm.plan(one)
+    assert s.n_nodes == 1 and s.n_fluid == 1
+    s = lbm.plan(one, propagation="aa")
+    assert s.pdf_bytes >= 19 * 8
+    with pytest.raises(lbm.LBMError):
+        lbm.plan(one, propagation="aa", layout="aos")

@@ -266,3 +266,21 @@ def test_aa_matches_two_lattice_bitwise_free(L):
         a.step(7)
         b.step(7)
         assert rel_maxabs(a.export(), b.export()) <= 1e-15
+
+
+@pytest.mark.parametrize("kw", [{}, {"layout": "aos"}, {"bounce": "halfway"}, {"propagation": "aa"},
+                                {"addressing": "list", "bounce": "halfway"}])
+def test_degenerate_lattices(L, kw):
+    """1-node and thin lattices (every neighbour is the node itself or a
+    wrap-around), and a geometry without fluid, behave like the oracle."""
+    for shape in ((1, 1, 1), (1, 3, 1), (2, 1, 5)):
+        mask = np.zeros(shape, dtype=np.uint8)
+        bounce = kw.get("bounce", "fullway")
+        f0 = random_state(mask, seed=1, amplitude=0.05, bounce=bounce)
+        got, ref, _ = _case(mask, 9, L, f0=f0, g=(1e-4, -1e-4, 2e-5), **kw)
+        assert rel_maxabs(got, ref) <= TOL, (shape, kw)
+    solid = np.ones((3, 4, 5), dtype=np.uint8)
+    lat = L.Lattice(solid, **kw)
+    lat.step(3)
+    st = lat.macroscopic()
+    assert st["nonfinite"] == 0 and st["u_max"] == 0.0
