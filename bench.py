@@ -213,7 +213,8 @@ def main():
                          ("soa_f16_shifted", dict(storage="f16s")),
                          ("soa_f16_shifted_stochastic", dict(storage="f16sr")),
                          ("soa_f64_halfway", dict(bounce="halfway")),
-                         ("aa_soa_f64", dict(propagation="aa"))]:
+                         ("aa_soa_f64", dict(propagation="aa")),
+                         ("push_soa_f64", dict(propagation="push"))]:
             log("variant %s" % name)
             lat, r = run_variant(mask, args.steps, args.warmup, **kw)
             variants[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
@@ -224,6 +225,8 @@ def main():
         for name, kw in [("list_spheres384_f64", dict(addressing="list", bounce="halfway")),
                          ("aa_list_spheres384_f64", dict(addressing="list", bounce="halfway",
                                                          propagation="aa")),
+                         ("push_list_spheres384_f64", dict(addressing="list", bounce="halfway",
+                                                           propagation="push")),
                          ("direct_spheres384_f64", dict(addressing="direct", bounce="halfway"))]:
             lat, r = run_variant(smask, args.steps, args.warmup, **kw)
             r["porosity"] = phi

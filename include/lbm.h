@@ -86,6 +86,8 @@ extern "C" {
 #define LBM_AA 1             /* AA pattern, one lattice updated in place:
                                 alternating node-local (even) and
                                 neighbour (odd) kernels (Sect. 3)          */
+#define LBM_OS_PUSH 2        /* one step, two lattices, push flavour: read
+                                the node, collide, scatter to neighbours   */
 
 #define LBM_FULLWAY 0        /* solids store and reverse populations       */
 #define LBM_HALFWAY 1        /* mid-link reflection in the same step       */
@@ -110,8 +112,9 @@ typedef struct {
   int32_t cu_slots;         /* at most this many sweep workgroups per
                                compute unit (reserved LDS caps residency);
                                0 = no cap                                  */
-  int32_t propagation;      /* LBM_OS | LBM_AA (AA: SOA layout; pdf_b is
-                               not used and may be NULL)                   */
+  int32_t propagation;      /* LBM_OS (pull) | LBM_AA | LBM_OS_PUSH (AA and
+                               push: SOA layout; AA uses pdf_a only and
+                               pdf_b may be NULL)                          */
   double tau_plus;          /* > 1/2; kinematic viscosity (tau+ - 1/2)/3   */
   double magic_lambda;      /* Lambda > 0                                  */
   double g[3];              /* body-force density, lattice units           */

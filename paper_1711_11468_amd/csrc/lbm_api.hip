@@ -65,9 +65,12 @@ static int validate(const lbm_params* p) {
   }
   if (p->pad < -1 || p->pad > (1 << 24)) { set_error("pad must be -1 or in [0, 2^24]"); return LBM_EINVAL; }
   if (p->cu_slots < 0 || p->cu_slots > 64) { set_error("cu_slots must be in [0, 64]"); return LBM_EINVAL; }
-  if (p->propagation != LBM_OS && p->propagation != LBM_AA) { set_error("bad propagation"); return LBM_EINVAL; }
-  if (p->propagation == LBM_AA && p->layout != LBM_SOA) {
-    set_error("the AA pattern is implemented for the SOA layout");
+  if (p->propagation != LBM_OS && p->propagation != LBM_AA && p->propagation != LBM_OS_PUSH) {
+    set_error("bad propagation");
+    return LBM_EINVAL;
+  }
+  if (p->propagation != LBM_OS && p->layout != LBM_SOA) {
+    set_error("the AA and push propagations are implemented for the SOA layout");
     return LBM_EINVAL;
   }
   for (int a = 0; a < 3; ++a)
@@ -174,7 +177,7 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
   if (N >= 0x7fffffffLL) { set_error("lattice too large"); return LBM_EOVERFLOW; }
   rc = plan_sizes(params, count_fluid(params, mask_host), &s);
   if (rc) return rc;
-  const bool two = params->propagation == LBM_OS;
+  const bool two = params->propagation != LBM_AA;
   if (!bufs->pdf_a || (two && !bufs->pdf_b) || !bufs->mask || !bufs->scratch) {
     set_error("pdf_a, pdf_b (one-step propagation), mask and scratch are required");
     return LBM_EINVAL;
@@ -210,7 +213,12 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
   // 512 threads: one workgroup covers a 512-node row in one pass, which
   // measured fastest for the one-step sweeps (the list sweep likes it too);
   // the in-place AA kernels measured faster with 256.
-  c->block = params->block ? params->block : (params->propagation == LBM_AA ? 256 : 512);
+  // default workgroup sizes as measured: 512 for the one-step pull rows, 256
+  // for AA, 128 for the scattered stores of the list push
+  c->block = params->block ? params->block
+             : params->propagation == LBM_AA ? 256
+             : (params->propagation == LBM_OS_PUSH && params->addressing == LBM_LIST) ? 128
+             : 512;
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) { delete c; return hip_fail(e, "hipGetDevice"); }
 

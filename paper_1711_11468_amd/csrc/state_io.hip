@@ -16,7 +16,9 @@ static View make_view(const lbm_ctx* c) {
   v.adj = c->b.adj;
   v.node_map = c->b.node_map;
   v.fluid_index = c->b.fluid_index;
-  v.aa = c->p.propagation == LBM_AA ? (c->aa_odd ? 2 : 1) : 0;
+  // push buffers hold the canonical state in place, like an AA lattice after
+  // an even number of updates
+  v.aa = c->p.propagation == LBM_AA ? (c->aa_odd ? 2 : 1) : (c->p.propagation == LBM_OS_PUSH ? 1 : 0);
   if (c->p.storage == LBM_F16_SHIFTED || c->p.storage == LBM_F16_SHIFTED_SR) {
     v.scale = ldexpf(1.0f, c->p.f16_scale_log2);
     v.inv_scale = ldexpf(1.0f, -c->p.f16_scale_log2);
@@ -79,7 +81,7 @@ hipError_t launch_build_adjacency(lbm_ctx* c) {
   const int nf = (int)c->s.n_fluid;
   if (nf == 0) return hipSuccess;
   hipLaunchKernelGGL(k_build_adjacency, dim3(grid_for(nf, 256)), dim3(256), 0, c->stream,
-                     make_view(c), nf, c->p.propagation == LBM_AA ? 1 : 0, c->b.adj);
+                     make_view(c), nf, c->p.propagation == LBM_OS ? 0 : 1, c->b.adj);
   return hipGetLastError();
 }
 

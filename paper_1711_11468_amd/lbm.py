@@ -21,7 +21,7 @@ SOA, AOS = 0, 1
 DIRECT, LIST = 0, 1
 F64, F32_SHIFTED, F16_SHIFTED, F16_SHIFTED_SR = 0, 1, 2, 3
 FULLWAY, HALFWAY = 0, 1
-OS, AA = 0, 1
+OS, AA, OS_PUSH = 0, 1, 2
 VERIFY_SLAB, VERIFY_DUCT, VERIFY_REFERENCE = 0, 1, 2
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, ENONFINITE, ENOTCONV = 0, -1, -2, -3, -4, -5, -6
 
@@ -29,7 +29,7 @@ _LAYOUTS = {"soa": SOA, "aos": AOS}
 _ADDR = {"direct": DIRECT, "list": LIST}
 _STORAGE = {"f64": F64, "f32s": F32_SHIFTED, "f16s": F16_SHIFTED, "f16sr": F16_SHIFTED_SR}
 _BOUNCE = {"fullway": FULLWAY, "halfway": HALFWAY}
-_PROP = {"os": OS, "aa": AA}
+_PROP = {"os": OS, "aa": AA, "push": OS_PUSH}
 ELEM_BYTES = {F64: 8, F32_SHIFTED: 4, F16_SHIFTED: 2, F16_SHIFTED_SR: 2}
 
 
@@ -201,7 +201,7 @@ class Lattice:
 
         self._t = {"pdf_a": alloc(s.pdf_bytes), "mask": alloc(s.mask_bytes),
                    "scratch": alloc(s.scratch_bytes)}
-        if self.params.propagation == OS:
+        if self.params.propagation != AA:
             self._t["pdf_b"] = alloc(s.pdf_bytes)
         if self.params.addressing == LIST:
             self._t["adj"] = alloc(s.adj_bytes)

@@ -25,7 +25,9 @@ FORMS = [
     ("os-pull-soa", dict()),
     ("os-pull-aos", dict(layout="aos")),
     ("os-pull-soa-halfway", dict(bounce="halfway")),
+    ("os-push-soa", dict(propagation="push")),
     ("list-os-pull-soa", dict(addressing="list", bounce="halfway")),
+    ("list-os-push-soa", dict(addressing="list", bounce="halfway", propagation="push")),
     ("aa-soa", dict(propagation="aa")),
     ("list-aa-soa", dict(addressing="list", bounce="halfway", propagation="aa")),
 ]

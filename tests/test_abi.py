@@ -122,3 +122,8 @@ def test_plan_degenerate_geometries():
     assert s.pdf_bytes >= 19 * 8
     with pytest.raises(lbm.LBMError):
         lbm.plan(one, propagation="aa", layout="aos")
+    with pytest.raises(lbm.LBMError):
+        lbm.plan(one, propagation="push", layout="aos")
+    m = np.zeros((8, 6, 5), dtype=np.uint8)
+    pull, push = lbm.plan(m), lbm.plan(m, propagation="push")
+    assert push.bytes_per_update == pull.bytes_per_update and push.pdf_bytes == pull.pdf_bytes

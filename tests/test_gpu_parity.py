@@ -268,8 +268,45 @@ def test_aa_matches_two_lattice_bitwise_free(L):
         assert rel_maxabs(a.export(), b.export()) <= 1e-15
 
 
+@pytest.mark.parametrize("kw", [{"bounce": "fullway"}, {"bounce": "halfway"},
+                                {"addressing": "list", "bounce": "halfway"},
+                                {"bounce": "fullway", "storage": "f64", "block": 64}])
+def test_push_random_state(L, kw):
+    """One-step push kernels (read the node, collide, scatter to the
+    neighbours) against the oracle from a random state with random solids
+    and a 3-component force, on a row that spans several blocks with a
+    ragged tail."""
+    mask = I.random_solid_mask(131, 9, 7, seed=14, fraction=0.2)
+    f0 = random_state(mask, seed=15, amplitude=0.02, bounce=kw["bounce"])
+    got, ref, lat = _case(mask, 13, L, f0=f0, propagation="push", g=(1e-4, 3e-5, -2e-5),
+                          tau_plus=0.9, magic=3 / 16, **kw)
+    assert rel_maxabs(got, ref) <= TOL
+    st = lat.macroscopic()
+    assert abs(st["mass"] - f0.sum()) <= 1e-13 * f0.sum()
+
+
+def test_push_and_pull_agree_stepwise(L):
+    """Push and pull one-step sweeps give the same states step by step (to
+    round-off) on the channel, and a state imported into a push lattice
+    continues like the pull lattice it came from."""
+    mask = I.channel_mask(64, 20, 18)
+    a = L.Lattice(mask, g=(1e-5, 0, 0), propagation="push")
+    b = L.Lattice(mask, g=(1e-5, 0, 0))
+    for k in range(3):
+        a.step(5)
+        b.step(5)
+        assert rel_maxabs(a.export(), b.export()) <= 1e-15
+    c = L.Lattice(mask, g=(1e-5, 0, 0), propagation="push")
+    c.import_(b.export())
+    b.step(4)
+    c.step(4)
+    assert rel_maxabs(c.export(), b.export()) <= 1e-15
+
+
 @pytest.mark.parametrize("kw", [{}, {"layout": "aos"}, {"bounce": "halfway"}, {"propagation": "aa"},
-                                {"addressing": "list", "bounce": "halfway"}])
+                                {"propagation": "push"}, {"propagation": "push", "bounce": "halfway"},
+                                {"addressing": "list", "bounce": "halfway"},
+                                {"addressing": "list", "bounce": "halfway", "propagation": "push"}])
 def test_degenerate_lattices(L, kw):
     """1-node and thin lattices (every neighbour is the node itself or a
     wrap-around), and a geometry without fluid, behave like the oracle."""
