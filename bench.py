@@ -151,7 +151,8 @@ def measured_traffic():
             k, v = line.split(":", 1)
             vals[k] = v.strip()
     h = hashlib.sha256()
-    for f in ("paper_1711_11468_amd/csrc/sweep.hip", "paper_1711_11468_amd/csrc/d3q19.hpp"):
+    for f in ("paper_1711_11468_amd/csrc/sweep.hip", "paper_1711_11468_amd/csrc/d3q19.hpp",
+              "paper_1711_11468_amd/csrc/launch.hpp"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     if h.hexdigest()[:16] != vals.get("source_sha256_16"):

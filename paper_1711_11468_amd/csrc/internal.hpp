@@ -27,7 +27,13 @@ void set_error(const char* fmt, ...);
 inline void* pdf_buf(lbm_ctx* c, int which) { return which == 0 ? c->b.pdf_a : c->b.pdf_b; }
 
 // Launchers: each enqueues on c->stream and returns a hipError_t.
-hipError_t launch_sweep(lbm_ctx* c, const void* src, void* dst);
+// One update of the lattice: the one-step pull sweep (SoA direct or list),
+// its AoS form, the push form (src -> dst), or the AA pattern (in place on
+// buf, the kernel chosen by c->aa_odd).
+hipError_t launch_pull(lbm_ctx* c, const void* src, void* dst);
+hipError_t launch_pull_aos(lbm_ctx* c, const void* src, void* dst);
+hipError_t launch_push(lbm_ctx* c, const void* src, void* dst);
+hipError_t launch_aa(lbm_ctx* c, void* buf);
 hipError_t launch_fill_rest(lbm_ctx* c, void* buf);
 hipError_t launch_build_adjacency(lbm_ctx* c);
 hipError_t launch_build_links(lbm_ctx* c);

@@ -293,11 +293,15 @@ int lbm_step(lbm_ctx* c, int32_t n) {
   LBM_HIP(hipSetDevice(c->device), "hipSetDevice");
   for (int32_t k = 0; k < n; ++k) {
     if (c->p.propagation == LBM_AA) {
-      hipError_t e = launch_sweep(c, pdf_buf(c, 0), nullptr);
+      hipError_t e = launch_aa(c, pdf_buf(c, 0));
       if (e != hipSuccess) return hip_fail(e, "AA sweep launch");
       c->aa_odd = 1 - c->aa_odd;
     } else {
-      hipError_t e = launch_sweep(c, pdf_buf(c, c->cur), pdf_buf(c, 1 - c->cur));
+      const void* src = pdf_buf(c, c->cur);
+      void* dst = pdf_buf(c, 1 - c->cur);
+      hipError_t e = c->p.propagation == LBM_OS_PUSH ? launch_push(c, src, dst)
+                     : c->p.layout == LBM_AOS        ? launch_pull_aos(c, src, dst)
+                                                     : launch_pull(c, src, dst);
       if (e != hipSuccess) return hip_fail(e, "sweep launch");
       c->cur = 1 - c->cur;
     }

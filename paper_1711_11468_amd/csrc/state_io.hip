@@ -85,6 +85,34 @@ hipError_t launch_build_adjacency(lbm_ctx* c) {
   return hipGetLastError();
 }
 
+// Link words for half-way bounce-back on the full array: bit 0 = the node is
+// solid, bit i (1..18) = the pull source x - c_i is solid.
+__global__ void k_build_links(const uint8_t* __restrict__ mask, uint32_t* __restrict__ links,
+                              int nx, int ny, int nz) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (n >= N) return;
+  const int x = (int)(n % nx);
+  const int64_t r = n / nx;
+  const int y = (int)(r % ny), z = (int)(r / ny);
+  uint32_t w = mask[n] != 0 ? 1u : 0u;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int sx = wrap_sub(x, Vel::cx[i], nx);
+    const int sy = wrap_sub(y, Vel::cy[i], ny);
+    const int sz = wrap_sub(z, Vel::cz[i], nz);
+    if (mask[sx + (int64_t)nx * (sy + (int64_t)ny * sz)] != 0) w |= 1u << i;
+  }
+  links[n] = w;
+}
+
+hipError_t launch_build_links(lbm_ctx* c) {
+  const int64_t N = c->s.n_nodes;
+  hipLaunchKernelGGL(k_build_links, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, c->stream,
+                     c->b.mask, c->b.links, c->p.nx, c->p.ny, c->p.nz);
+  return hipGetLastError();
+}
+
 // ---- export ---------------------------------------------------------------
 template <class ST, int LAYOUT, int ADDR, int BB>
 __global__ void k_export(const typename ST::T* __restrict__ src, View v,

@@ -1,0 +1,135 @@
+// sweep_aa.hip - the AA pattern (Sect. 3): one lattice updated in place by
+// alternating node-local (even) and neighbour (odd) kernels; SoA layout,
+// direct and list addressing.
+#include "launch.hpp"
+
+namespace lbm {
+
+// Local (even) kernel: read a node's own 19 slots, collide, write f*_i into
+// the node's slot opp(i).  Neighbour (odd) kernel: population i of node x is
+// f*_i(x - c_i), which the local kernel left in slot opp(i) of x - c_i (or,
+// under half-way bounce-back from a solid x - c_i, in slot i of x itself);
+// after collision f*_i goes to slot i of x + c_i (or slot opp(i) of x when
+// x + c_i is solid), where the next local kernel reads it.  Every slot is
+// read and written by exactly one node, so both kernels are race-free in
+// place.  Under full-way bounce-back solid nodes are storage no-ops (their
+// reversal maps each slot onto itself) and are skipped.
+template <class ST, int BB, bool ODD>
+__global__ void __launch_bounds__(1024)
+k_aa_soa(typename ST::T* __restrict__ A, const uint8_t* __restrict__ mask,
+         const uint32_t* __restrict__ links, int nx, int ny, int nz, int64_t stride,
+         Collide<typename ST::R> k) {
+  using R = typename ST::R;
+  const int row = blockIdx.x;
+  const int y = row % ny;
+  const int z = row / ny;
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+  for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int n = x + nx * row;
+    uint32_t lk = 0;
+    bool solid;
+    if (BB == LBM_HALFWAY) {
+      lk = links[n];
+      solid = (lk & 1u) != 0;
+    } else {
+      solid = mask[n] != 0;
+    }
+    if (solid) continue;
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      int64_t at;
+      if (!ODD) {
+        at = (int64_t)i * stride + n;
+      } else {
+        const int sx = Vel::cx[i] == 1 ? xm : (Vel::cx[i] == -1 ? xp : x);
+        const int sy = Vel::cy[i] == 1 ? ym : (Vel::cy[i] == -1 ? yp : y);
+        const int sz = Vel::cz[i] == 1 ? zm : (Vel::cz[i] == -1 ? zp : z);
+        at = (int64_t)Vel::opp[i] * stride + (sx + nx * (sy + ny * sz));
+        if (BB == LBM_HALFWAY && i != 0 && ((lk >> i) & 1u)) at = (int64_t)i * stride + n;
+      }
+      f[i] = ST::load(A[at], k.inv_scale);
+    }
+    trt_collide<R, ST::kShifted>(f, k);
+    SrStream rs((uint32_t)n, k.step, ST::kStochastic);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      int64_t at;
+      if (!ODD) {
+        at = (int64_t)Vel::opp[i] * stride + n;
+      } else {
+        const int tx = Vel::cx[i] == 1 ? xp : (Vel::cx[i] == -1 ? xm : x);
+        const int ty = Vel::cy[i] == 1 ? yp : (Vel::cy[i] == -1 ? ym : y);
+        const int tz = Vel::cz[i] == 1 ? zp : (Vel::cz[i] == -1 ? zm : z);
+        at = (int64_t)i * stride + (tx + nx * (ty + ny * tz));
+        if (BB == LBM_HALFWAY && i != 0 && ((lk >> Vel::opp[i]) & 1u)) at = (int64_t)Vel::opp[i] * stride + n;
+      }
+      __builtin_nontemporal_store(ST::store(f[i], k.scale, rs.next()), &A[at]);
+    }
+  }
+}
+
+// List AA: the adjacency holds, for direction i, the slot the neighbour
+// kernel reads (opp(i) of the neighbour x - c_i, or i of the node itself when
+// that neighbour is solid); the slot it writes for direction i is the read
+// slot of opp(i).
+template <class ST, bool ODD>
+__global__ void __launch_bounds__(1024)
+k_aa_list(typename ST::T* __restrict__ A, const int32_t* __restrict__ adj, int nf,
+          int64_t stride, Collide<typename ST::R> k) {
+  using R = typename ST::R;
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nf) return;
+  R f[Q];
+  int32_t a[Q];
+  a[0] = m;
+#pragma unroll
+  for (int i = 1; i < Q; ++i)
+    a[i] = ODD ? adj[(int64_t)(i - 1) * stride + m] : (int32_t)((int64_t)i * stride + m);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) f[i] = ST::load(A[a[i]], k.inv_scale);
+  trt_collide<R, ST::kShifted>(f, k);
+  SrStream rs((uint32_t)m, k.step, ST::kStochastic);
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    __builtin_nontemporal_store(ST::store(f[i], k.scale, rs.next()), &A[a[Vel::opp[i]]]);
+}
+
+// One in-place update of buf; c->aa_odd selects the kernel.
+hipError_t launch_aa(lbm_ctx* c, void* buf) {
+  return with_storage(c->p, [&](auto st) -> hipError_t {
+    using ST = decltype(st);
+    using T = typename ST::T;
+    const lbm_params& p = c->p;
+    const auto k = make_collide<typename ST::R>(p, c->step);
+    T* A = (T*)buf;
+    const bool odd = c->aa_odd != 0;
+    const size_t lds = sweep_lds(c, 0);
+    if (p.addressing == LBM_LIST) {
+      const int nf = (int)c->s.n_fluid;
+      if (nf == 0) return hipSuccess;
+      const int blk = c->block;
+      const dim3 g((nf + blk - 1) / blk), b(blk);
+      if (odd) hipLaunchKernelGGL((k_aa_list<ST, true>), g, b, lds, c->stream, A, c->b.adj, nf, c->s.stride, k);
+      else hipLaunchKernelGGL((k_aa_list<ST, false>), g, b, lds, c->stream, A, c->b.adj, nf, c->s.stride, k);
+      return hipGetLastError();
+    }
+    const dim3 g((unsigned)p.ny * (unsigned)p.nz), b(row_block(c));
+#define LBM_AA_LAUNCH(BB, ODD)                                                                   \
+  hipLaunchKernelGGL((k_aa_soa<ST, BB, ODD>), g, b, lds, c->stream, A, c->b.mask, c->b.links, p.nx, \
+                     p.ny, p.nz, c->s.stride, k)
+    if (p.bounce == LBM_FULLWAY) {
+      if (odd) LBM_AA_LAUNCH(LBM_FULLWAY, true);
+      else LBM_AA_LAUNCH(LBM_FULLWAY, false);
+    } else {
+      if (odd) LBM_AA_LAUNCH(LBM_HALFWAY, true);
+      else LBM_AA_LAUNCH(LBM_HALFWAY, false);
+    }
+#undef LBM_AA_LAUNCH
+    return hipGetLastError();
+  });
+}
+
+}  // namespace lbm
