@@ -106,7 +106,8 @@ typedef struct {
   int32_t bounce;           /* LBM_FULLWAY | LBM_HALFWAY (LIST: HALFWAY)   */
   int32_t f16_scale_log2;   /* s for the F16 storages, 0..24; else ignored */
   int32_t block;            /* threads per workgroup, 0 = default; a
-                               multiple of 64 up to 1024                   */
+                               multiple of 64 up to 1024 (the AA kernels
+                               take at most 512 and cut larger values)     */
   int32_t pad;              /* extra elements between direction arrays
                                (SOA/LIST); -1 = automatic                  */
   int32_t cu_slots;         /* at most this many sweep workgroups per

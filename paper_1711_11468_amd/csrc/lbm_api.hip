@@ -213,10 +213,9 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
   // 512 threads: one workgroup covers a 512-node row in one pass, which
   // measured fastest for the one-step sweeps (the list sweep likes it too);
   // the in-place AA kernels measured faster with 256.
-  // default workgroup sizes as measured: 512 for the one-step pull rows, 256
-  // for AA, 128 for the scattered stores of the list push
+  // default workgroup sizes as measured: 512 for the row sweeps and AA, 128
+  // for the scattered stores of the list push
   c->block = params->block ? params->block
-             : params->propagation == LBM_AA ? 256
              : (params->propagation == LBM_OS_PUSH && params->addressing == LBM_LIST) ? 128
              : 512;
   hipError_t e = hipGetDevice(&c->device);
