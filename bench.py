@@ -78,6 +78,7 @@ def run_variant(mask, steps, warmup, diag=True, **kw):
         "kernel_ms": float(np.mean(per)),
         "bytes_per_update": lat.sizes.bytes_per_update,
         "n_sites": lat.sizes.n_sites,
+        "n_runs": lat.sizes.n_runs,
         "n_fluid": nf,
         "mass_rel_drift": abs(st["mass"] - lat.sizes.n_sites) / lat.sizes.n_sites
         if kw.get("addressing", "direct") == "direct" and kw.get("bounce", "fullway") == "fullway" else None,
@@ -228,6 +229,9 @@ def main():
                                                          propagation="aa")),
                          ("push_list_spheres384_f64", dict(addressing="list", bounce="halfway",
                                                            propagation="push")),
+                         ("ria_spheres384_f64", dict(addressing="ria", bounce="halfway")),
+                         ("aa_ria_spheres384_f64", dict(addressing="ria", bounce="halfway",
+                                                        propagation="aa")),
                          ("direct_spheres384_f64", dict(addressing="direct", bounce="halfway"))]:
             lat, r = run_variant(smask, args.steps, args.warmup, **kw)
             r["porosity"] = phi

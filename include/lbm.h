@@ -8,9 +8,11 @@
  * collision with a constant body force, and store the 19 results at the
  * node in a destination lattice (Sect. 3, "One Step Kernels", pull
  * variant; the non-temporal-store refinement of Sect. 3 is applied to every
- * store).  Lattices are represented as a full array with a flag field
- * ("direct" addressing) or as a fluid-node vector with an adjacency list
- * ("list", indirect addressing), Sect. 3 "Lattice Representation", in
+ * store of the one-step pull sweeps).  Beside it stand the AA pattern and
+ * the push flavour of Sect. 3.  Lattices are represented as a full array
+ * with a flag field ("direct" addressing) or as a fluid-node vector with an
+ * adjacency list ("list", indirect addressing, optionally run-length
+ * reduced), Sect. 3 "Lattice Representation", in
  * structure-of-arrays or array-of-structures layout (Sect. 3 "Data Layout").
  * Bounce-back is full-way or half-way (Sect. 2, Sect. 3.2); periodicity is
  * part of the index arithmetic or of the adjacency list (Sect. 3.2).
@@ -72,6 +74,11 @@ extern "C" {
 
 #define LBM_DIRECT 0         /* full array + flag field (all N nodes)      */
 #define LBM_LIST 1           /* fluid-node vector + int32 adjacency        */
+#define LBM_LIST_RIA 2       /* fluid-node vector with reduced indirect
+                                addressing (Sect. 3): runs of consecutive
+                                fluid nodes whose 18 source slots all
+                                advance by one with the node share one
+                                table entry; no per-node adjacency         */
 
 #define LBM_F64 0            /* double populations (the paper's storage)   */
 #define LBM_F32_SHIFTED 1    /* float  h = f - w, float collide            */
@@ -99,11 +106,11 @@ extern "C" {
 /* ---- parameter and buffer records ------------------------------------ */
 typedef struct {
   int32_t nx, ny, nz;       /* nodes per axis, walls included; each >= 1   */
-  int32_t layout;           /* LBM_SOA | LBM_AOS (LBM_LIST requires SOA)   */
-  int32_t addressing;       /* LBM_DIRECT | LBM_LIST                       */
+  int32_t layout;           /* LBM_SOA | LBM_AOS (the lists require SOA)   */
+  int32_t addressing;       /* LBM_DIRECT | LBM_LIST | LBM_LIST_RIA        */
   int32_t storage;          /* LBM_F64 | LBM_F32_SHIFTED | LBM_F16_SHIFTED
                                | LBM_F16_SHIFTED_SR                        */
-  int32_t bounce;           /* LBM_FULLWAY | LBM_HALFWAY (LIST: HALFWAY)   */
+  int32_t bounce;           /* LBM_FULLWAY | LBM_HALFWAY (lists: HALFWAY)  */
   int32_t f16_scale_log2;   /* s for the F16 storages, 0..24; else ignored */
   int32_t block;            /* threads per workgroup, 0 = default; a
                                multiple of 64 up to 1024 (the AA kernels
@@ -130,12 +137,15 @@ typedef struct {
   int64_t pdf_bytes;        /* size of EACH of pdf_a and pdf_b             */
   int64_t mask_bytes;       /* device mask: N bytes                        */
   int64_t adj_bytes;        /* LIST: 18*stride int32; else 0               */
-  int64_t fluid_index_bytes;/* LIST: Nf int32 (list -> node); else 0       */
-  int64_t node_map_bytes;   /* LIST: N int32 (node -> list or -1); else 0  */
+  int64_t fluid_index_bytes;/* LIST, LIST_RIA: Nf int32 (list -> node)     */
+  int64_t node_map_bytes;   /* LIST, LIST_RIA: N int32 (node -> list/-1)   */
   int64_t links_bytes;      /* DIRECT + HALFWAY: N uint32 link words       */
   int64_t u_prev_bytes;     /* 3*n_sites doubles for the residual          */
   int64_t scratch_bytes;    /* reduction partials                          */
   double bytes_per_update;  /* algorithmic HBM bytes per site update       */
+  int64_t n_runs;           /* LIST_RIA: number of runs; else 0            */
+  int64_t ria_bytes;        /* LIST_RIA: run tables (library-internal
+                               layout, filled at init); else 0             */
 } lbm_sizes;
 
 typedef struct {            /* device pointers, caller-owned               */
@@ -143,12 +153,13 @@ typedef struct {            /* device pointers, caller-owned               */
   void* pdf_b;              /* pdf_bytes, 256-byte aligned (LBM_OS only)   */
   uint8_t* mask;            /* mask_bytes                                  */
   int32_t* adj;             /* LIST only, else NULL                        */
-  int32_t* fluid_index;     /* LIST only, else NULL                        */
-  int32_t* node_map;        /* LIST only, else NULL                        */
+  int32_t* fluid_index;     /* LIST and LIST_RIA, else NULL                */
+  int32_t* node_map;        /* LIST and LIST_RIA, else NULL                */
   uint32_t* links;          /* DIRECT + HALFWAY only (bit 0: node solid,
                                bit i: neighbour x - c_i solid), else NULL  */
   double* u_prev;           /* optional (NULL: no residual)                */
   void* scratch;            /* scratch_bytes                               */
+  void* ria;                /* LIST_RIA only (ria_bytes), else NULL        */
 } lbm_buffers;
 
 typedef struct {
@@ -176,9 +187,10 @@ typedef struct lbm_ctx lbm_ctx;
 /* ---- entry points ---------------------------------------------------- */
 
 /* Sizes of every buffer for a parameter set and a host mask (N bytes).
- * Counts fluid nodes; validates parameters (tau+ > 1/2, Lambda > 0,
- * dims >= 1 and <= 65535 on y and z, N < 2^31, LIST needs
- * 19*stride < 2^31).  Allocates nothing.  Errors: EINVAL, EOVERFLOW. */
+ * Counts fluid nodes (and, for LIST_RIA, the runs); validates parameters
+ * (tau+ > 1/2, Lambda > 0, dims >= 1 and <= 65535 on y and z, N < 2^31,
+ * the lists need 19*stride < 2^31).  Allocates nothing.
+ * Errors: EINVAL, EOVERFLOW. */
 int lbm_plan(const lbm_params* params, const uint8_t* mask_host, lbm_sizes* out);
 
 /* Geometry set-up (Sect. 3 "Lattice Representation"; Sect. 3.2): copies the
@@ -187,7 +199,13 @@ int lbm_plan(const lbm_params* params, const uint8_t* mask_host, lbm_sizes* out)
  * the node map and the adjacency list (18 int32 per node: the slot a pull
  * reads for direction i, which is the neighbour's slot, wrapped
  * periodically, or the node's own opposite slot when the neighbour is solid
- * - half-way bounce-back); then fills both PDF buffers with the rest state
+ * - half-way bounce-back); for LIST_RIA builds the fluid-node vector, the
+ * node map and the run tables instead of the adjacency list (a run is a
+ * maximal set of consecutive fluid nodes of one x-row, away from the x
+ * wrap, whose 18 neighbours x - c_i have the same fluid/solid status as
+ * those of the previous node; along a run every source slot advances by
+ * one, so one table entry per run serves all its nodes, Sect. 3
+ * "Lattice Representation"); then fills both PDF buffers with the rest state
  * f_i = w_i.  `stream` is a hipStream_t (NULL = default stream).  On
  * success *out owns host metadata only.  Synchronises the stream.
  * Errors: EINVAL, EOVERFLOW, ENOMEM, EDEVICE. */

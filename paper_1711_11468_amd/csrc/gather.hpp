@@ -45,6 +45,22 @@ __device__ __forceinline__ void node_xyz(const View& v, int64_t n, int& x, int& 
   z = (int)(r / v.ny);
 }
 
+// Slot of direction i (1..18) for list node m, as the adjacency list holds
+// it: read from the list, or, for the run-length list (no per-node
+// adjacency), derived from the node map.  Pull semantics (slot i of the
+// neighbour x - c_i, else slot opp(i) of the node) unless the lattice is an
+// AA lattice after an odd number of updates (slot opp(i) of the neighbour,
+// else slot i of the node).
+__device__ __forceinline__ int64_t list_slot(const View& v, int m, int i) {
+  if (v.adj) return v.adj[(int64_t)(i - 1) * v.stride + m];
+  int x, y, z;
+  node_xyz(v, v.fluid_index[m], x, y, z);
+  const int t = v.node_map[wrap_node(v, x - Vel::cx[i], y - Vel::cy[i], z - Vel::cz[i])];
+  const bool aa = v.aa == 2;
+  return t >= 0 ? (int64_t)(aa ? Vel::opp[i] : i) * v.stride + t
+                : (int64_t)(aa ? i : Vel::opp[i]) * v.stride + m;
+}
+
 template <class ST>
 __device__ __forceinline__ double to_f64(typename ST::T raw, int i, const View& v) {
   if (ST::kShifted) return (double)ST::load(raw, v.inv_scale) + weight(i);
@@ -76,7 +92,7 @@ __device__ __forceinline__ bool gather_canonical(const typename ST::T* __restric
     f[0] = to_f64<ST>(src[m], 0, v);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const int64_t at = v.aa == 1 ? (int64_t)i * v.stride + m : (int64_t)v.adj[(int64_t)(i - 1) * v.stride + m];
+      const int64_t at = v.aa == 1 ? (int64_t)i * v.stride + m : list_slot(v, m, i);
       f[i] = to_f64<ST>(src[at], i, v);
     }
     return true;
@@ -151,11 +167,12 @@ template <int V>
 using IC = std::integral_constant<int, V>;
 
 // Call f(storage_tag, layout, addressing, bounce) with compile-time tags for
-// the parameter combination of p (LIST implies SOA and half-way).
+// the parameter combination of p (both lists imply SOA and half-way and
+// share the LIST tag: node-wise access differs only inside list_slot).
 template <class F>
 hipError_t dispatch(const lbm_params& p, F&& f) {
   auto by_store = [&](auto st) -> hipError_t {
-    if (p.addressing == LBM_LIST) return f(st, IC<LBM_SOA>{}, IC<LBM_LIST>{}, IC<LBM_HALFWAY>{});
+    if (p.addressing != LBM_DIRECT) return f(st, IC<LBM_SOA>{}, IC<LBM_LIST>{}, IC<LBM_HALFWAY>{});
     if (p.layout == LBM_SOA) {
       if (p.bounce == LBM_FULLWAY) return f(st, IC<LBM_SOA>{}, IC<LBM_DIRECT>{}, IC<LBM_FULLWAY>{});
       return f(st, IC<LBM_SOA>{}, IC<LBM_DIRECT>{}, IC<LBM_HALFWAY>{});

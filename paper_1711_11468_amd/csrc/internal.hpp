@@ -18,9 +18,23 @@ struct lbm_ctx {
   int u_prev_valid;    // u_prev holds the velocity of a previous call
   int block;           // threads per workgroup for the sweeps
   int device;
+  // LIST_RIA run tables, carved out of b.ria: run_start[n_runs + 1] (first
+  // list index of each run, then n_fluid), run_adj[18][run_stride] (the
+  // slot of direction i for the run's first node), chunk_run[ceil(Nf/64)]
+  // (the run of node 64c) and run_delta[Nf] (run of node m minus the run
+  // of its 64-node chunk, < 64).
+  int64_t n_runs;
+  int64_t run_stride;
+  int32_t* run_start;
+  int32_t* run_adj;
+  int32_t* chunk_run;
+  uint8_t* run_delta;
 };
 
 namespace lbm {
+
+// True for the two fluid-list addressings.
+inline bool is_list(const lbm_params& p) { return p.addressing != LBM_DIRECT; }
 
 void set_error(const char* fmt, ...);
 
@@ -34,6 +48,12 @@ hipError_t launch_pull(lbm_ctx* c, const void* src, void* dst);
 hipError_t launch_pull_aos(lbm_ctx* c, const void* src, void* dst);
 hipError_t launch_push(lbm_ctx* c, const void* src, void* dst);
 hipError_t launch_aa(lbm_ctx* c, void* buf);
+// Run-length list (LIST_RIA): the pull and push sweeps and the AA
+// neighbour kernel (the AA local kernel needs no addressing).
+hipError_t launch_pull_ria(lbm_ctx* c, const void* src, void* dst);
+hipError_t launch_push_ria(lbm_ctx* c, const void* src, void* dst);
+hipError_t launch_aa_ria_odd(lbm_ctx* c, void* buf);
+hipError_t launch_build_run_adj(lbm_ctx* c);
 hipError_t launch_fill_rest(lbm_ctx* c, void* buf);
 hipError_t launch_build_adjacency(lbm_ctx* c);
 hipError_t launch_build_links(lbm_ctx* c);

@@ -47,10 +47,13 @@ static int validate(const lbm_params* p) {
   if (!(p->tau_plus > 0.5)) { set_error("tau_plus must exceed 1/2"); return LBM_EINVAL; }
   if (!(p->magic_lambda > 0.0)) { set_error("magic_lambda must be positive"); return LBM_EINVAL; }
   if (p->layout != LBM_SOA && p->layout != LBM_AOS) { set_error("bad layout"); return LBM_EINVAL; }
-  if (p->addressing != LBM_DIRECT && p->addressing != LBM_LIST) { set_error("bad addressing"); return LBM_EINVAL; }
+  if (p->addressing != LBM_DIRECT && p->addressing != LBM_LIST && p->addressing != LBM_LIST_RIA) {
+    set_error("bad addressing");
+    return LBM_EINVAL;
+  }
   if (p->storage < LBM_F64 || p->storage > LBM_F16_SHIFTED_SR) { set_error("bad storage"); return LBM_EINVAL; }
   if (p->bounce != LBM_FULLWAY && p->bounce != LBM_HALFWAY) { set_error("bad bounce"); return LBM_EINVAL; }
-  if (p->addressing == LBM_LIST && (p->layout != LBM_SOA || p->bounce != LBM_HALFWAY)) {
+  if (is_list(*p) && (p->layout != LBM_SOA || p->bounce != LBM_HALFWAY)) {
     set_error("list addressing requires SOA layout and half-way bounce-back");
     return LBM_EINVAL;
   }
@@ -78,14 +81,64 @@ static int validate(const lbm_params* p) {
   return LBM_OK;
 }
 
-static int plan_sizes(const lbm_params* p, int64_t n_fluid, lbm_sizes* s) {
+// Byte offsets of the run tables inside the ria buffer (layout in lbm_ctx).
+struct RiaLayout {
+  int64_t run_stride, start_off, adj_off, chunk_off, delta_off, bytes;
+};
+
+static RiaLayout ria_layout(int64_t n_runs, int64_t n_fluid) {
+  RiaLayout L;
+  L.run_stride = round_up(n_runs < 1 ? 1 : n_runs, 64);
+  L.start_off = 0;
+  L.adj_off = round_up((n_runs + 1) * 4, 256);
+  L.chunk_off = L.adj_off + round_up((Q - 1) * L.run_stride * 4, 256);
+  L.delta_off = L.chunk_off + round_up(((n_fluid + 63) / 64 + 1) * 4, 256);
+  L.bytes = L.delta_off + round_up(n_fluid < 1 ? 1 : n_fluid, 256);
+  return L;
+}
+
+// Runs of the run-length list.  List node m (x-fastest order) continues the
+// run of m - 1 iff node m - 1 is its x-neighbour in the same row, neither
+// pull source of the pair wraps around in x (2 <= x <= nx - 2), and for
+// every direction the sources x - c_i of both nodes are both fluid or both
+// solid: then each source slot of m is that of m - 1 plus one.  Fills
+// is_start[m] when the pointer is given; returns the number of runs.
+static int64_t find_runs(const lbm_params* p, const uint8_t* mask, uint8_t* is_start) {
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  int64_t runs = 0, m = 0;
+  for (int z = 0; z < nz; ++z) {
+    for (int y = 0; y < ny; ++y) {
+      const int64_t row = (int64_t)nx * (y + (int64_t)ny * z);
+      // the nine source rows (y - c_y, z - c_z) of this row
+      const uint8_t* src_row[Q];
+      for (int i = 0; i < Q; ++i) {
+        const int sy = (y - Vel::cy[i] + ny) % ny, sz = (z - Vel::cz[i] + nz) % nz;
+        src_row[i] = mask + (int64_t)nx * (sy + (int64_t)ny * sz);
+      }
+      for (int x = 0; x < nx; ++x) {
+        if (mask[row + x] != 0) continue;
+        bool start = x < 2 || x > nx - 2 || mask[row + x - 1] != 0;
+        for (int i = 1; i < Q && !start; ++i) {
+          const int sx = x - Vel::cx[i];
+          start = (src_row[i][sx] != 0) != (src_row[i][sx - 1] != 0);
+        }
+        if (start) ++runs;
+        if (is_start) is_start[m] = start ? 1 : 0;
+        ++m;
+      }
+    }
+  }
+  return runs;
+}
+
+static int plan_sizes(const lbm_params* p, int64_t n_fluid, int64_t n_runs, lbm_sizes* s) {
   const int64_t N = (int64_t)p->nx * p->ny * p->nz;
   if (N >= 0x7fffffffLL) { set_error("lattice of %lld nodes exceeds 32-bit node indices", (long long)N); return LBM_EOVERFLOW; }
   const int es = elem_size(p->storage);
   memset(s, 0, sizeof *s);
   s->n_nodes = N;
   s->n_fluid = n_fluid;
-  s->n_sites = p->addressing == LBM_LIST ? n_fluid : N;
+  s->n_sites = is_list(*p) ? n_fluid : N;
   if (p->layout == LBM_AOS) {
     s->stride = Q;
     s->pdf_bytes = round_up(N * Q * es, 256);
@@ -102,14 +155,18 @@ static int plan_sizes(const lbm_params* p, int64_t n_fluid, lbm_sizes* s) {
     s->pdf_bytes = st * Q * es;
   }
   s->mask_bytes = round_up(N, 256);
-  if (p->addressing == LBM_LIST) {
+  if (is_list(*p)) {
     if (s->stride * Q >= 0x7fffffffLL) {
       set_error("list of %lld fluid nodes overflows int32 adjacency entries", (long long)n_fluid);
       return LBM_EOVERFLOW;
     }
-    s->adj_bytes = round_up(s->stride * (Q - 1) * 4, 256);
+    if (p->addressing == LBM_LIST) s->adj_bytes = round_up(s->stride * (Q - 1) * 4, 256);
     s->fluid_index_bytes = round_up((n_fluid < 1 ? 1 : n_fluid) * 4, 256);
     s->node_map_bytes = round_up(N * 4, 256);
+  }
+  if (p->addressing == LBM_LIST_RIA) {
+    s->n_runs = n_runs;
+    s->ria_bytes = ria_layout(n_runs, n_fluid).bytes;
   }
   const bool links = p->addressing == LBM_DIRECT && p->bounce == LBM_HALFWAY;
   if (links) s->links_bytes = round_up(N * 4, 256);
@@ -117,12 +174,17 @@ static int plan_sizes(const lbm_params* p, int64_t n_fluid, lbm_sizes* s) {
   s->scratch_bytes = round_up((int64_t)(4096 + 1) * kStatSlots * 8, 256);
   // Algorithmic HBM bytes per site update: 19 loads + 19 stores of one
   // element, plus the flag byte (direct, full-way), the link word (direct,
-  // half-way) or 18 int32 adjacency entries (list).
-  // The AA pattern on the list reads the adjacency in the neighbour kernel
-  // only: 18*4 B every other update (Table 1: 340 B/FLUP in FP64).
-  const double adj_bytes = p->propagation == LBM_AA ? 2.0 * (Q - 1) : 4.0 * (Q - 1);
-  s->bytes_per_update =
-      2.0 * Q * es + (p->addressing == LBM_LIST ? adj_bytes : (links ? 4.0 : 1.0));
+  // half-way), 18 int32 adjacency entries (list) or, for the run-length
+  // list, the run offset byte, the chunk word per 64 nodes and the run's
+  // start and 18 entries once per run.
+  // The AA pattern on the lists reads the addressing in the neighbour kernel
+  // only: every other update (Table 1: 340 B/FLUP for the FP64 list).
+  double addr = links ? 4.0 : 1.0;
+  if (p->addressing == LBM_LIST) addr = 4.0 * (Q - 1);
+  if (p->addressing == LBM_LIST_RIA)
+    addr = 1.0 + 4.0 / 64 + (n_fluid > 0 ? 4.0 * Q * (double)n_runs / (double)n_fluid : 0.0);
+  if (is_list(*p) && p->propagation == LBM_AA) addr *= 0.5;
+  s->bytes_per_update = 2.0 * Q * es + addr;
   return LBM_OK;
 }
 
@@ -162,7 +224,8 @@ int lbm_plan(const lbm_params* params, const uint8_t* mask_host, lbm_sizes* out)
   if (!mask_host || !out) { set_error("mask_host and out must be non-NULL"); return LBM_EINVAL; }
   const int64_t N = (int64_t)params->nx * params->ny * params->nz;
   if (N >= 0x7fffffffLL) { set_error("lattice too large"); return LBM_EOVERFLOW; }
-  return plan_sizes(params, count_fluid(params, mask_host), out);
+  const int64_t runs = params->addressing == LBM_LIST_RIA ? find_runs(params, mask_host, nullptr) : 0;
+  return plan_sizes(params, count_fluid(params, mask_host), runs, out);
 }
 
 int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* mask_host,
@@ -175,7 +238,20 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
   lbm_sizes s;
   const int64_t N = (int64_t)params->nx * params->ny * params->nz;
   if (N >= 0x7fffffffLL) { set_error("lattice too large"); return LBM_EOVERFLOW; }
-  rc = plan_sizes(params, count_fluid(params, mask_host), &s);
+  const bool ria = params->addressing == LBM_LIST_RIA;
+  std::vector<uint8_t> run_starts;
+  int64_t runs = 0;
+  if (ria) {
+    const int64_t nf = count_fluid(params, mask_host);
+    try {
+      run_starts.resize((size_t)(nf > 0 ? nf : 1));
+    } catch (...) {
+      set_error("host allocation failed");
+      return LBM_ENOMEM;
+    }
+    runs = find_runs(params, mask_host, run_starts.data());
+  }
+  rc = plan_sizes(params, count_fluid(params, mask_host), runs, &s);
   if (rc) return rc;
   const bool two = params->propagation != LBM_AA;
   if (!bufs->pdf_a || (two && !bufs->pdf_b) || !bufs->mask || !bufs->scratch) {
@@ -190,6 +266,10 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
     set_error("list addressing needs adj, fluid_index and node_map");
     return LBM_EINVAL;
   }
+  if (ria && (!bufs->ria || !bufs->fluid_index || !bufs->node_map)) {
+    set_error("run-length list addressing needs ria, fluid_index and node_map");
+    return LBM_EINVAL;
+  }
   if (s.links_bytes > 0 && !bufs->links) {
     set_error("direct addressing with half-way bounce-back needs the links buffer");
     return LBM_EINVAL;
@@ -199,10 +279,21 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
   c->p = *params;
   c->s = s;
   c->b = *bufs;
-  if (params->addressing != LBM_LIST) {
-    c->b.adj = nullptr;
+  if (params->addressing != LBM_LIST) c->b.adj = nullptr;
+  if (!is_list(*params)) {
     c->b.fluid_index = nullptr;
     c->b.node_map = nullptr;
+  }
+  if (!ria) c->b.ria = nullptr;
+  c->n_runs = runs;
+  if (ria) {
+    const RiaLayout L = ria_layout(runs, s.n_fluid);
+    char* base = (char*)c->b.ria;
+    c->run_stride = L.run_stride;
+    c->run_start = (int32_t*)(base + L.start_off);
+    c->run_adj = (int32_t*)(base + L.adj_off);
+    c->chunk_run = (int32_t*)(base + L.chunk_off);
+    c->run_delta = (uint8_t*)(base + L.delta_off);
   }
   if (s.links_bytes == 0) c->b.links = nullptr;
   c->stream = (hipStream_t)stream;
@@ -210,13 +301,11 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
   c->aa_odd = 0;
   c->step = 0;
   c->u_prev_valid = 0;
-  // 512 threads: one workgroup covers a 512-node row in one pass, which
-  // measured fastest for the one-step sweeps (the list sweep likes it too);
-  // the in-place AA kernels measured faster with 256.
-  // default workgroup sizes as measured: 512 for the row sweeps and AA, 128
-  // for the scattered stores of the list push
+  // default workgroup sizes as measured: 512 for the row sweeps (one
+  // workgroup covers a 512-node row in one pass), the list sweeps and AA;
+  // 128 for the scattered stores of the list push
   c->block = params->block ? params->block
-             : (params->propagation == LBM_OS_PUSH && params->addressing == LBM_LIST) ? 128
+             : (params->propagation == LBM_OS_PUSH && is_list(*params)) ? 128
              : 512;
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) { delete c; return hip_fail(e, "hipGetDevice"); }
@@ -231,7 +320,7 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
     e = launch_build_links(c);
     if (e != hipSuccess) return fail(e, "link words kernel");
   }
-  if (params->addressing == LBM_LIST) {
+  if (is_list(*params)) {
     // Fluid-node vector in x-fastest order and the node -> list map.
     std::vector<int32_t> fidx, nmap;
     try {
@@ -256,8 +345,42 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
     if (e != hipSuccess) return fail(e, "fluid index upload");
     e = hipMemcpyAsync(c->b.node_map, nmap.data(), (size_t)N * 4, hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return fail(e, "node map upload");
-    e = launch_build_adjacency(c);
-    if (e != hipSuccess) return fail(e, "adjacency kernel");
+    std::vector<int32_t> rstart, chunk;
+    std::vector<uint8_t> delta;
+    if (ria) {
+      // run starts, the run of each 64-node chunk's first node and each
+      // node's offset from it (a chunk holds at most 64 runs)
+      const int64_t nf = s.n_fluid;
+      try {
+        rstart.resize((size_t)runs + 1);
+        chunk.resize((size_t)((nf + 63) / 64 + 1));
+        delta.resize((size_t)(nf > 0 ? nf : 1));
+      } catch (...) {
+        delete c;
+        set_error("host allocation failed");
+        return LBM_ENOMEM;
+      }
+      int64_t r = -1;
+      for (int64_t k = 0; k < nf; ++k) {
+        if (run_starts[k]) rstart[++r] = (int32_t)k;
+        if (k % 64 == 0) chunk[k / 64] = (int32_t)r;
+        delta[k] = (uint8_t)(r - chunk[k / 64]);
+      }
+      rstart[runs] = (int32_t)nf;
+      e = hipMemcpyAsync(c->run_start, rstart.data(), (size_t)(runs + 1) * 4, hipMemcpyHostToDevice,
+                         c->stream);
+      if (e == hipSuccess && nf > 0)
+        e = hipMemcpyAsync(c->chunk_run, chunk.data(), (size_t)((nf + 63) / 64) * 4,
+                           hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess && nf > 0)
+        e = hipMemcpyAsync(c->run_delta, delta.data(), (size_t)nf, hipMemcpyHostToDevice, c->stream);
+      if (e != hipSuccess) return fail(e, "run table upload");
+      e = launch_build_run_adj(c);
+      if (e != hipSuccess) return fail(e, "run table kernel");
+    } else {
+      e = launch_build_adjacency(c);
+      if (e != hipSuccess) return fail(e, "adjacency kernel");
+    }
     // the host vectors are released below only after the copies completed
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(e, "adjacency sync");
@@ -298,9 +421,12 @@ int lbm_step(lbm_ctx* c, int32_t n) {
     } else {
       const void* src = pdf_buf(c, c->cur);
       void* dst = pdf_buf(c, 1 - c->cur);
-      hipError_t e = c->p.propagation == LBM_OS_PUSH ? launch_push(c, src, dst)
-                     : c->p.layout == LBM_AOS        ? launch_pull_aos(c, src, dst)
-                                                     : launch_pull(c, src, dst);
+      const bool ria = c->p.addressing == LBM_LIST_RIA;
+      hipError_t e;
+      if (c->p.propagation == LBM_OS_PUSH) e = ria ? launch_push_ria(c, src, dst) : launch_push(c, src, dst);
+      else if (ria) e = launch_pull_ria(c, src, dst);
+      else if (c->p.layout == LBM_AOS) e = launch_pull_aos(c, src, dst);
+      else e = launch_pull(c, src, dst);
       if (e != hipSuccess) return hip_fail(e, "sweep launch");
       c->cur = 1 - c->cur;
     }

@@ -61,9 +61,8 @@ hipError_t launch_fill_rest(lbm_ctx* c, void* buf) {
 // slot opp(i)*stride + m when the neighbour is solid (half-way bounce-back).
 // For the AA pattern the neighbour kernel reads the reversed slots instead:
 // opp(i)*stride + map(x - c_i), or i*stride + m at a solid neighbour.
-__global__ void k_build_adjacency(View v, int nf, int aa, int32_t* __restrict__ adj) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= nf) return;
+__device__ __forceinline__ void adjacency_of(const View& v, int m, int aa, int32_t* out,
+                                             int64_t out_stride) {
   int x, y, z;
   node_xyz(v, v.fluid_index[m], x, y, z);
 #pragma unroll
@@ -73,8 +72,14 @@ __global__ void k_build_adjacency(View v, int nf, int aa, int32_t* __restrict__ 
     const int dn = aa ? Vel::opp[i] : i;     // direction slot at the neighbour
     const int ds = aa ? i : Vel::opp[i];     // direction slot at the node itself
     const int64_t s = t >= 0 ? (int64_t)dn * v.stride + t : (int64_t)ds * v.stride + m;
-    adj[(int64_t)(i - 1) * v.stride + m] = (int32_t)s;
+    out[(int64_t)(i - 1) * out_stride] = (int32_t)s;
   }
+}
+
+__global__ void k_build_adjacency(View v, int nf, int aa, int32_t* __restrict__ adj) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nf) return;
+  adjacency_of(v, m, aa, adj + m, v.stride);
 }
 
 hipError_t launch_build_adjacency(lbm_ctx* c) {
@@ -82,6 +87,23 @@ hipError_t launch_build_adjacency(lbm_ctx* c) {
   if (nf == 0) return hipSuccess;
   hipLaunchKernelGGL(k_build_adjacency, dim3(grid_for(nf, 256)), dim3(256), 0, c->stream,
                      make_view(c), nf, c->p.propagation == LBM_OS ? 0 : 1, c->b.adj);
+  return hipGetLastError();
+}
+
+// Run-length list: the same 18 entries, once per run, for the run's first
+// node; node m of run r then uses entry + (m - run_start[r]).
+__global__ void k_build_run_adj(View v, const int32_t* __restrict__ run_start, int64_t n_runs,
+                                int aa, int64_t run_stride, int32_t* __restrict__ run_adj) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_runs) return;
+  adjacency_of(v, run_start[r], aa, run_adj + r, run_stride);
+}
+
+hipError_t launch_build_run_adj(lbm_ctx* c) {
+  if (c->n_runs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_build_run_adj, dim3(grid_for(c->n_runs, 256)), dim3(256), 0, c->stream,
+                     make_view(c), c->run_start, c->n_runs, c->p.propagation == LBM_OS ? 0 : 1,
+                     c->run_stride, c->run_adj);
   return hipGetLastError();
 }
 

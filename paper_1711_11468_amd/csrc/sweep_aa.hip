@@ -106,6 +106,7 @@ k_aa_list(typename ST::T* __restrict__ A, const int32_t* __restrict__ adj, int n
 
 // One in-place update of buf; c->aa_odd selects the kernel.
 hipError_t launch_aa(lbm_ctx* c, void* buf) {
+  if (c->p.addressing == LBM_LIST_RIA && c->aa_odd) return launch_aa_ria_odd(c, buf);
   return with_storage(c->p, [&](auto st) -> hipError_t {
     using ST = decltype(st);
     using T = typename ST::T;
@@ -114,7 +115,7 @@ hipError_t launch_aa(lbm_ctx* c, void* buf) {
     T* A = (T*)buf;
     const bool odd = c->aa_odd != 0;
     const size_t lds = sweep_lds(c, 0);
-    if (p.addressing == LBM_LIST) {
+    if (is_list(p)) {  // the local kernel of the run-length list lands here too
       const int nf = (int)c->s.n_fluid;
       if (nf == 0) return hipSuccess;
       const int blk = c->block < kAaMaxBlock ? c->block : kAaMaxBlock;

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "liblbm.so")
 
 SOA, AOS = 0, 1
-DIRECT, LIST = 0, 1
+DIRECT, LIST, LIST_RIA = 0, 1, 2
 F64, F32_SHIFTED, F16_SHIFTED, F16_SHIFTED_SR = 0, 1, 2, 3
 FULLWAY, HALFWAY = 0, 1
 OS, AA, OS_PUSH = 0, 1, 2
@@ -26,7 +26,7 @@ VERIFY_SLAB, VERIFY_DUCT, VERIFY_REFERENCE = 0, 1, 2
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, ENONFINITE, ENOTCONV = 0, -1, -2, -3, -4, -5, -6
 
 _LAYOUTS = {"soa": SOA, "aos": AOS}
-_ADDR = {"direct": DIRECT, "list": LIST}
+_ADDR = {"direct": DIRECT, "list": LIST, "ria": LIST_RIA}
 _STORAGE = {"f64": F64, "f32s": F32_SHIFTED, "f16s": F16_SHIFTED, "f16sr": F16_SHIFTED_SR}
 _BOUNCE = {"fullway": FULLWAY, "halfway": HALFWAY}
 _PROP = {"os": OS, "aa": AA, "push": OS_PUSH}
@@ -50,7 +50,8 @@ class Sizes(ctypes.Structure):
                 ("adj_bytes", ctypes.c_int64), ("fluid_index_bytes", ctypes.c_int64),
                 ("node_map_bytes", ctypes.c_int64), ("links_bytes", ctypes.c_int64),
                 ("u_prev_bytes", ctypes.c_int64),
-                ("scratch_bytes", ctypes.c_int64), ("bytes_per_update", ctypes.c_double)]
+                ("scratch_bytes", ctypes.c_int64), ("bytes_per_update", ctypes.c_double),
+                ("n_runs", ctypes.c_int64), ("ria_bytes", ctypes.c_int64)]
 
 
 class Buffers(ctypes.Structure):
@@ -58,7 +59,7 @@ class Buffers(ctypes.Structure):
                 ("mask", ctypes.c_void_p), ("adj", ctypes.c_void_p),
                 ("fluid_index", ctypes.c_void_p), ("node_map", ctypes.c_void_p),
                 ("links", ctypes.c_void_p), ("u_prev", ctypes.c_void_p),
-                ("scratch", ctypes.c_void_p)]
+                ("scratch", ctypes.c_void_p), ("ria", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -205,6 +206,9 @@ class Lattice:
             self._t["pdf_b"] = alloc(s.pdf_bytes)
         if self.params.addressing == LIST:
             self._t["adj"] = alloc(s.adj_bytes)
+        if self.params.addressing == LIST_RIA:
+            self._t["ria"] = alloc(s.ria_bytes)
+        if self.params.addressing != DIRECT:
             self._t["fluid_index"] = alloc(s.fluid_index_bytes)
             self._t["node_map"] = alloc(s.node_map_bytes)
         if s.links_bytes > 0:

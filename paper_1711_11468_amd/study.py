@@ -28,8 +28,10 @@ FORMS = [
     ("os-push-soa", dict(propagation="push")),
     ("list-os-pull-soa", dict(addressing="list", bounce="halfway")),
     ("list-os-push-soa", dict(addressing="list", bounce="halfway", propagation="push")),
+    ("list-ria-os-pull-soa", dict(addressing="ria", bounce="halfway")),
     ("aa-soa", dict(propagation="aa")),
     ("list-aa-soa", dict(addressing="list", bounce="halfway", propagation="aa")),
+    ("list-aa-ria-soa", dict(addressing="ria", bounce="halfway", propagation="aa")),
 ]
 
 

@@ -127,3 +127,79 @@ def test_plan_degenerate_geometries():
     m = np.zeros((8, 6, 5), dtype=np.uint8)
     pull, push = lbm.plan(m), lbm.plan(m, propagation="push")
     assert push.bytes_per_update == pull.bytes_per_update and push.pdf_bytes == pull.pdf_bytes
+
+
+def _runs_by_definition(mask):
+    """Run starts of the run-length list, from its definition, in numpy:
+    a fluid node continues the run of its x-predecessor when that node is
+    fluid, neither pull source of the pair wraps in x (2 <= x <= nx-2), and
+    every pair of sources x - c_i has the same fluid/solid status."""
+    from oracle import oracle as O
+    c = O.table()[0]
+    nz, ny, nx = mask.shape
+    solid = mask != 0
+    start = np.zeros(mask.shape, dtype=bool)
+    start[:, :, :2] = True
+    start[:, :, nx - 1:] = True
+    start |= np.roll(solid, 1, axis=2)
+    for i in range(1, 19):
+        src = np.roll(solid, (c[i][2], c[i][1], c[i][0]), axis=(0, 1, 2))  # status of x - c_i
+        start |= src != np.roll(src, 1, axis=2)
+    return start[~solid]
+
+
+def _pull_adjacency(mask):
+    """Pull slots (direction-major, list order) of every fluid node."""
+    from oracle import oracle as O
+    c = O.table()[0]
+    opp = O.table()[2]
+    nz, ny, nx = mask.shape
+    fl = mask.reshape(-1) == 0
+    nmap = np.full(mask.size, -1, dtype=np.int64)
+    nmap[fl] = np.arange(fl.sum())
+    z, y, x = np.unravel_index(np.flatnonzero(fl), mask.shape)
+    m = np.arange(fl.sum())
+    nf = len(m)
+    adj = np.empty((19, nf), dtype=np.int64)
+    for i in range(19):
+        sn = ((x - c[i][0]) % nx) + nx * (((y - c[i][1]) % ny) + ny * ((z - c[i][2]) % nz))
+        t = nmap[sn]
+        adj[i] = np.where(t >= 0, i * nf + t, opp[i] * nf + m)
+    return adj
+
+
+@pytest.mark.parametrize("which", ["duct", "random", "spheres", "tiny"])
+def test_ria_runs(which):
+    """lbm_plan's run count equals the count from the definition, and along
+    each such run every pull slot advances by exactly one (so one table
+    entry per run reproduces the adjacency list)."""
+    masks = {"duct": I.channel_mask(70, 9, 8),
+             "random": I.random_solid_mask(40, 9, 7, seed=2, fraction=0.25),
+             "spheres": I.spheres_mask(48, 40, 36, seed=3, porosity=0.6, rmin=2, rmax=5)[0],
+             "tiny": np.zeros((2, 1, 3), dtype=np.uint8)}
+    mask = masks[which]
+    start = _runs_by_definition(mask)
+    s = lbm.plan(mask, addressing="ria", bounce="halfway")
+    assert s.n_runs == int(start.sum())
+    assert s.adj_bytes == 0 and s.ria_bytes >= 18 * 4 * s.n_runs
+    adj = _pull_adjacency(mask)
+    cont = ~start
+    cont[0] = False
+    idx = np.flatnonzero(cont)
+    assert np.array_equal(adj[:, idx], adj[:, idx - 1] + 1)
+    if which == "duct":
+        assert s.n_runs == 3 * 7 * 6  # x = 0, x = 1 .. nx-2, x = nx-1 in every fluid row
+        nf = s.n_fluid
+        expect = 304 + 1 + 4 / 64 + 4 * 19 * s.n_runs / nf
+        assert abs(s.bytes_per_update - expect) < 1e-9
+
+
+def test_ria_validation():
+    m = np.zeros((4, 4, 4), dtype=np.uint8)
+    for kw in (dict(layout="aos"), dict(bounce="fullway")):
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.plan(m, addressing="ria", **kw)
+        assert e.value.code == lbm.EINVAL
+    s = lbm.plan(m, addressing="ria", bounce="halfway", propagation="aa")
+    s1 = lbm.plan(m, addressing="ria", bounce="halfway")
+    assert s.bytes_per_update - 304 == pytest.approx((s1.bytes_per_update - 304) / 2)

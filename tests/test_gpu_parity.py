@@ -93,7 +93,8 @@ def test_import_export_roundtrip(L):
     """Import followed by export returns the canonical state bit for bit."""
     mask = I.random_solid_mask(11, 7, 6, seed=8, fraction=0.25)
     for kw in ({"layout": "soa", "bounce": "fullway"}, {"layout": "aos", "bounce": "halfway"},
-               {"addressing": "list", "bounce": "halfway"}):
+               {"addressing": "list", "bounce": "halfway"}, {"addressing": "ria", "bounce": "halfway"},
+               {"addressing": "ria", "bounce": "halfway", "propagation": "aa"}):
         f0 = random_state(mask, seed=1, amplitude=0.05, bounce=kw["bounce"])
         lat = L.Lattice(mask, **kw)
         lat.import_(f0)
@@ -148,12 +149,14 @@ def test_full_size_channel_512_sampled(L):
     assert abs(st["mass"] - n ** 3) <= 1e-12 * n ** 3
 
 
-def test_full_size_spheres_384_list_sampled(L):
-    """384^3 porous box (list addressing) against the windowed oracle."""
+@pytest.mark.parametrize("addressing", ["list", "ria"])
+def test_full_size_spheres_384_list_sampled(L, addressing):
+    """384^3 porous box (fluid list, plain or run-length) against the
+    windowed oracle."""
     n, steps = 384, 8
     mask, phi, _ = I.spheres_mask(n, n, n, seed=0, porosity=0.4, rmin=8, rmax=16)
     phys = dict(tau_plus=0.8, magic=3 / 16, g=(1e-6, 0.0, 0.0))
-    lat = L.Lattice(mask, addressing="list", bounce="halfway", **phys)
+    lat = L.Lattice(mask, addressing=addressing, bounce="halfway", **phys)
     lat.step(steps)
     rng = np.random.default_rng(7)
     fluid = np.flatnonzero(mask.reshape(-1) == 0)
@@ -306,7 +309,9 @@ def test_push_and_pull_agree_stepwise(L):
 @pytest.mark.parametrize("kw", [{}, {"layout": "aos"}, {"bounce": "halfway"}, {"propagation": "aa"},
                                 {"propagation": "push"}, {"propagation": "push", "bounce": "halfway"},
                                 {"addressing": "list", "bounce": "halfway"},
-                                {"addressing": "list", "bounce": "halfway", "propagation": "push"}])
+                                {"addressing": "list", "bounce": "halfway", "propagation": "push"},
+                                {"addressing": "ria", "bounce": "halfway"},
+                                {"addressing": "ria", "bounce": "halfway", "propagation": "aa"}])
 def test_degenerate_lattices(L, kw):
     """1-node and thin lattices (every neighbour is the node itself or a
     wrap-around), and a geometry without fluid, behave like the oracle."""
@@ -321,3 +326,44 @@ def test_degenerate_lattices(L, kw):
     lat.step(3)
     st = lat.macroscopic()
     assert st["nonfinite"] == 0 and st["u_max"] == 0.0
+
+
+def _ria_geometries():
+    # short runs (random solids), long runs crossing 64-node chunks (a duct
+    # 131 long), and pores of a sphere pack
+    duct = I.channel_mask(131, 7, 6)
+    spheres, _, _ = I.spheres_mask(70, 12, 10, seed=4, porosity=0.7, rmin=2, rmax=4)
+    return {"random": I.random_solid_mask(67, 9, 7, seed=21, fraction=0.3),
+            "duct": duct, "spheres": spheres}
+
+
+@pytest.mark.parametrize("geom", ["random", "duct", "spheres"])
+@pytest.mark.parametrize("prop,steps", [("os", 17), ("aa", 24), ("aa", 25), ("push", 17)])
+def test_ria_random_state(L, geom, prop, steps):
+    """Run-length list (reduced indirect addressing) for every propagation
+    form against the oracle, from a random state with a 3-component force."""
+    mask = _ria_geometries()[geom]
+    f0 = random_state(mask, seed=22, amplitude=0.02, bounce="halfway")
+    got, ref, lat = _case(mask, steps, L, f0=f0, addressing="ria", bounce="halfway",
+                          propagation=prop, g=(1e-4, -3e-5, 2e-5), tau_plus=0.9, magic=3 / 16)
+    assert lat.sizes.n_runs > 0 and lat.sizes.adj_bytes == 0
+    assert rel_maxabs(got, ref) <= TOL
+    st = lat.macroscopic()
+    assert abs(st["mass"] - f0.sum()) <= 1e-13 * f0.sum()
+
+
+def test_ria_and_list_agree(L):
+    """The run-length list reads exactly the slots the adjacency list names:
+    both lists give the same states to round-off, step by step, for pull,
+    push and AA."""
+    mask = _ria_geometries()["spheres"]
+    f0 = random_state(mask, seed=5, amplitude=0.02, bounce="halfway")
+    for prop in ("os", "push", "aa"):
+        a = L.Lattice(mask, addressing="ria", bounce="halfway", propagation=prop, g=(1e-5, 0, 0))
+        b = L.Lattice(mask, addressing="list", bounce="halfway", propagation=prop, g=(1e-5, 0, 0))
+        a.import_(f0)
+        b.import_(f0)
+        for _ in range(3):
+            a.step(5)
+            b.step(5)
+            assert rel_maxabs(a.export(), b.export()) <= 1e-15, prop
