@@ -120,9 +120,8 @@ typedef struct {
   int32_t cu_slots;         /* at most this many sweep workgroups per
                                compute unit (reserved LDS caps residency);
                                0 = no cap                                  */
-  int32_t propagation;      /* LBM_OS (pull) | LBM_AA | LBM_OS_PUSH (AA and
-                               push: SOA layout; AA uses pdf_a only and
-                               pdf_b may be NULL)                          */
+  int32_t propagation;      /* LBM_OS (pull) | LBM_AA | LBM_OS_PUSH (AA
+                               uses pdf_a only; pdf_b may be NULL)         */
   double tau_plus;          /* > 1/2; kinematic viscosity (tau+ - 1/2)/3   */
   double magic_lambda;      /* Lambda > 0                                  */
   double g[3];              /* body-force density, lattice units           */

@@ -72,10 +72,7 @@ static int validate(const lbm_params* p) {
     set_error("bad propagation");
     return LBM_EINVAL;
   }
-  if (p->propagation != LBM_OS && p->layout != LBM_SOA) {
-    set_error("the AA and push propagations are implemented for the SOA layout");
-    return LBM_EINVAL;
-  }
+
   for (int a = 0; a < 3; ++a)
     if (!(p->g[a] == p->g[a]) || p->g[a] > 1e30 || p->g[a] < -1e30) { set_error("bad g"); return LBM_EINVAL; }
   return LBM_OK;
@@ -179,12 +176,18 @@ static int plan_sizes(const lbm_params* p, int64_t n_fluid, int64_t n_runs, lbm_
   // start and 18 entries once per run.
   // The AA pattern on the lists reads the addressing in the neighbour kernel
   // only: every other update (Table 1: 340 B/FLUP for the FP64 list).
+  // On the full array, solid nodes move populations only where they store
+  // them: the full-way pull and push sweeps reverse them; half-way sweeps
+  // and the AA kernels read just the solid node's flag or link word.
   double addr = links ? 4.0 : 1.0;
   if (p->addressing == LBM_LIST) addr = 4.0 * (Q - 1);
   if (p->addressing == LBM_LIST_RIA)
     addr = 1.0 + 4.0 / 64 + (n_fluid > 0 ? 4.0 * Q * (double)n_runs / (double)n_fluid : 0.0);
   if (is_list(*p) && p->propagation == LBM_AA) addr *= 0.5;
-  s->bytes_per_update = 2.0 * Q * es + addr;
+  double moved = 2.0 * Q * es;
+  const bool solids_move = p->bounce == LBM_FULLWAY && p->propagation != LBM_AA;
+  if (!is_list(*p) && !solids_move && N > 0) moved *= (double)n_fluid / (double)N;
+  s->bytes_per_update = moved + addr;
   return LBM_OK;
 }
 

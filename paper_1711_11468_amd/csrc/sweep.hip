@@ -40,6 +40,7 @@ k_sweep_soa(const typename ST::T* __restrict__ src, typename ST::T* __restrict__
     if (BB == LBM_HALFWAY) {
       lk = links[n];
       solid = (lk & 1u) != 0;
+      if (solid) continue;  // half-way: solid nodes hold nothing
     } else {
       solid = mask[n] != 0;
     }
@@ -55,13 +56,11 @@ k_sweep_soa(const typename ST::T* __restrict__ src, typename ST::T* __restrict__
       f[i] = ST::load(src[at], k.inv_scale);
     }
     SrStream rs((uint32_t)n, k.step, ST::kStochastic);
-    if (solid) {
-      if (BB == LBM_FULLWAY) {
+    if (BB == LBM_FULLWAY && solid) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-          __builtin_nontemporal_store(ST::store(f[Vel::opp[i]], k.scale, rs.next()),
-                                      &dst[(int64_t)i * stride + n]);
-      }
+      for (int i = 0; i < Q; ++i)
+        __builtin_nontemporal_store(ST::store(f[Vel::opp[i]], k.scale, rs.next()),
+                                    &dst[(int64_t)i * stride + n]);
       continue;
     }
     trt_collide<R, ST::kShifted>(f, k);

@@ -1,6 +1,7 @@
 // sweep_aa.hip - the AA pattern (Sect. 3): one lattice updated in place by
-// alternating node-local (even) and neighbour (odd) kernels; SoA layout,
-// direct and list addressing.
+// alternating node-local (even) and neighbour (odd) kernels; direct
+// addressing in SoA and AoS layout, list addressing.
+#include "gather.hpp"
 #include "launch.hpp"
 
 namespace lbm {
@@ -22,9 +23,9 @@ constexpr int kAaMaxBlock = 512;
 // read and written by exactly one node, so both kernels are race-free in
 // place.  Under full-way bounce-back solid nodes are storage no-ops (their
 // reversal maps each slot onto itself) and are skipped.
-template <class ST, int BB, bool ODD>
+template <class ST, int LAYOUT, int BB, bool ODD>
 __global__ void __launch_bounds__(kAaMaxBlock)
-k_aa_soa(typename ST::T* __restrict__ A, const uint8_t* __restrict__ mask,
+k_aa_direct(typename ST::T* __restrict__ A, const uint8_t* __restrict__ mask,
          const uint32_t* __restrict__ links, int nx, int ny, int nz, int64_t stride,
          Collide<typename ST::R> k) {
   using R = typename ST::R;
@@ -50,13 +51,13 @@ k_aa_soa(typename ST::T* __restrict__ A, const uint8_t* __restrict__ mask,
     for (int i = 0; i < Q; ++i) {
       int64_t at;
       if (!ODD) {
-        at = (int64_t)i * stride + n;
+        at = vslot<LAYOUT>(n, i, stride);
       } else {
         const int sx = Vel::cx[i] == 1 ? xm : (Vel::cx[i] == -1 ? xp : x);
         const int sy = Vel::cy[i] == 1 ? ym : (Vel::cy[i] == -1 ? yp : y);
         const int sz = Vel::cz[i] == 1 ? zm : (Vel::cz[i] == -1 ? zp : z);
-        at = (int64_t)Vel::opp[i] * stride + (sx + nx * (sy + ny * sz));
-        if (BB == LBM_HALFWAY && i != 0 && ((lk >> i) & 1u)) at = (int64_t)i * stride + n;
+        at = vslot<LAYOUT>(sx + (int64_t)nx * (sy + (int64_t)ny * sz), Vel::opp[i], stride);
+        if (BB == LBM_HALFWAY && i != 0 && ((lk >> i) & 1u)) at = vslot<LAYOUT>(n, i, stride);
       }
       f[i] = ST::load(A[at], k.inv_scale);
     }
@@ -66,13 +67,13 @@ k_aa_soa(typename ST::T* __restrict__ A, const uint8_t* __restrict__ mask,
     for (int i = 0; i < Q; ++i) {
       int64_t at;
       if (!ODD) {
-        at = (int64_t)Vel::opp[i] * stride + n;
+        at = vslot<LAYOUT>(n, Vel::opp[i], stride);
       } else {
         const int tx = Vel::cx[i] == 1 ? xp : (Vel::cx[i] == -1 ? xm : x);
         const int ty = Vel::cy[i] == 1 ? yp : (Vel::cy[i] == -1 ? ym : y);
         const int tz = Vel::cz[i] == 1 ? zp : (Vel::cz[i] == -1 ? zm : z);
-        at = (int64_t)i * stride + (tx + nx * (ty + ny * tz));
-        if (BB == LBM_HALFWAY && i != 0 && ((lk >> Vel::opp[i]) & 1u)) at = (int64_t)Vel::opp[i] * stride + n;
+        at = vslot<LAYOUT>(tx + (int64_t)nx * (ty + (int64_t)ny * tz), i, stride);
+        if (BB == LBM_HALFWAY && i != 0 && ((lk >> Vel::opp[i]) & 1u)) at = vslot<LAYOUT>(n, Vel::opp[i], stride);
       }
       A[at] = ST::store(f[i], k.scale, rs.next());
     }
@@ -126,16 +127,23 @@ hipError_t launch_aa(lbm_ctx* c, void* buf) {
     }
     const int rb = row_block(c);
     const dim3 g((unsigned)p.ny * (unsigned)p.nz), b(rb < kAaMaxBlock ? rb : kAaMaxBlock);
-#define LBM_AA_LAUNCH(BB, ODD)                                                                   \
-  hipLaunchKernelGGL((k_aa_soa<ST, BB, ODD>), g, b, lds, c->stream, A, c->b.mask, c->b.links, p.nx, \
-                     p.ny, p.nz, c->s.stride, k)
-    if (p.bounce == LBM_FULLWAY) {
-      if (odd) LBM_AA_LAUNCH(LBM_FULLWAY, true);
-      else LBM_AA_LAUNCH(LBM_FULLWAY, false);
+#define LBM_AA_LAUNCH(LAY, BB, ODD)                                                              \
+  hipLaunchKernelGGL((k_aa_direct<ST, LAY, BB, ODD>), g, b, lds, c->stream, A, c->b.mask,      \
+                     c->b.links, p.nx, p.ny, p.nz, c->s.stride, k)
+#define LBM_AA_LAUNCH_L(LAY)                                  \
+  if (p.bounce == LBM_FULLWAY) {                              \
+    if (odd) LBM_AA_LAUNCH(LAY, LBM_FULLWAY, true);           \
+    else LBM_AA_LAUNCH(LAY, LBM_FULLWAY, false);              \
+  } else {                                                    \
+    if (odd) LBM_AA_LAUNCH(LAY, LBM_HALFWAY, true);           \
+    else LBM_AA_LAUNCH(LAY, LBM_HALFWAY, false);              \
+  }
+    if (p.layout == LBM_SOA) {
+      LBM_AA_LAUNCH_L(LBM_SOA)
     } else {
-      if (odd) LBM_AA_LAUNCH(LBM_HALFWAY, true);
-      else LBM_AA_LAUNCH(LBM_HALFWAY, false);
+      LBM_AA_LAUNCH_L(LBM_AOS)
     }
+#undef LBM_AA_LAUNCH_L
 #undef LBM_AA_LAUNCH
     return hipGetLastError();
   });

@@ -1,5 +1,6 @@
 // sweep_push.hip - the one-step update, push flavour (Sect. 3, "One Step
-// Kernels"); SoA layout, direct and list addressing.
+// Kernels"); direct addressing in SoA and AoS layout, list addressing.
+#include "gather.hpp"
 #include "launch.hpp"
 
 namespace lbm {
@@ -11,9 +12,9 @@ namespace lbm {
 // nontemporal form measured about 6 % slower here).  Full-way solid
 // nodes send their reversed populations on; under half-way bounce-back a
 // population aimed at a solid node lands in slot opp(i) of the node itself.
-template <class ST, int BB>
+template <class ST, int LAYOUT, int BB>
 __global__ void __launch_bounds__(1024)
-k_push_soa(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
+k_push_direct(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
            const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx,
            int ny, int nz, int64_t stride, Collide<typename ST::R> k) {
   using R = typename ST::R;
@@ -36,7 +37,7 @@ k_push_soa(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ 
     }
     R f[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = ST::load(src[(int64_t)i * stride + n], k.inv_scale);
+    for (int i = 0; i < Q; ++i) f[i] = ST::load(src[vslot<LAYOUT>(n, i, stride)], k.inv_scale);
     if (!solid) {
       trt_collide<R, ST::kShifted>(f, k);
     } else {
@@ -52,9 +53,9 @@ k_push_soa(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ 
       const int tx = Vel::cx[i] == 1 ? xp : (Vel::cx[i] == -1 ? xm : x);
       const int ty = Vel::cy[i] == 1 ? yp : (Vel::cy[i] == -1 ? ym : y);
       const int tz = Vel::cz[i] == 1 ? zp : (Vel::cz[i] == -1 ? zm : z);
-      int64_t at = (int64_t)i * stride + (tx + nx * (ty + ny * tz));
+      int64_t at = vslot<LAYOUT>(tx + (int64_t)nx * (ty + (int64_t)ny * tz), i, stride);
       // link bit opp(i): x - c_opp(i) = x + c_i is solid
-      if (BB == LBM_HALFWAY && i != 0 && ((lk >> Vel::opp[i]) & 1u)) at = (int64_t)Vel::opp[i] * stride + n;
+      if (BB == LBM_HALFWAY && i != 0 && ((lk >> Vel::opp[i]) & 1u)) at = vslot<LAYOUT>(n, Vel::opp[i], stride);
       dst[at] = ST::store(f[i], k.scale, rs.next());
     }
   }
@@ -100,12 +101,17 @@ hipError_t launch_push(lbm_ctx* c, const void* src, void* dst) {
       return hipGetLastError();
     }
     const dim3 g((unsigned)p.ny * (unsigned)p.nz), b(row_block(c));
-    if (p.bounce == LBM_FULLWAY)
-      hipLaunchKernelGGL((k_push_soa<ST, LBM_FULLWAY>), g, b, lds, c->stream, s, d, c->b.mask,
-                         c->b.links, p.nx, p.ny, p.nz, c->s.stride, k);
-    else
-      hipLaunchKernelGGL((k_push_soa<ST, LBM_HALFWAY>), g, b, lds, c->stream, s, d, c->b.mask,
-                         c->b.links, p.nx, p.ny, p.nz, c->s.stride, k);
+#define LBM_PUSH_LAUNCH(LAY, BB)                                                                \
+  hipLaunchKernelGGL((k_push_direct<ST, LAY, BB>), g, b, lds, c->stream, s, d, c->b.mask,     \
+                     c->b.links, p.nx, p.ny, p.nz, c->s.stride, k)
+    if (p.layout == LBM_SOA) {
+      if (p.bounce == LBM_FULLWAY) LBM_PUSH_LAUNCH(LBM_SOA, LBM_FULLWAY);
+      else LBM_PUSH_LAUNCH(LBM_SOA, LBM_HALFWAY);
+    } else {
+      if (p.bounce == LBM_FULLWAY) LBM_PUSH_LAUNCH(LBM_AOS, LBM_FULLWAY);
+      else LBM_PUSH_LAUNCH(LBM_AOS, LBM_HALFWAY);
+    }
+#undef LBM_PUSH_LAUNCH
     return hipGetLastError();
   });
 }

@@ -2,7 +2,8 @@
 
 1. Every sweep form on the paper's channel of 500 x 100 x 100 nodes
    (Sect. 4.2 uses it for all kernel comparisons; 4,802,000 fluid nodes).
-2. The `blocks` geometry (Sect. 2; the paper's Fig. 4 study): cubic
+2. The staircase pipe of the same size (Sect. 2), every form but AoS.
+3. The `blocks` geometry (Sect. 2; the paper's Fig. 4 study): cubic
    obstacles of growing edge inside the same 500 x 100 x 100 channel, gap
    equal to the edge, for the direct and list kernels.
 
@@ -64,12 +65,20 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     import torch  # noqa: F401
-    res = {"channel_500x100x100": {}, "blocks_500x100x100": []}
+    res = {"channel_500x100x100": {}, "pipe_500x100x100": {}, "blocks_500x100x100": []}
     ch = I.channel_mask(500, 100, 100)
     for name, kw in FORMS:
         r = time_form(ch, args.steps, args.warmup, **kw)
         res["channel_500x100x100"][name] = r
         print("channel %-20s %8.1f MFLUP/s  %6.0f GB/s  %.1f B/FLUP" % (
+            name, r["mflups"], r["gbs"], r["bytes_per_fluid_update"]), flush=True)
+    pipe = I.pipe_mask(500, 100, 100)
+    for name, kw in FORMS:
+        if name == "os-pull-aos":
+            continue
+        r = time_form(pipe, args.steps, args.warmup, **kw)
+        res["pipe_500x100x100"][name] = r
+        print("pipe    %-20s %8.1f MFLUP/s  %6.0f GB/s  %.1f B/FLUP" % (
             name, r["mflups"], r["gbs"], r["bytes_per_fluid_update"]), flush=True)
     for edge in (1, 2, 4, 8, 16):
         m = I.blocks_mask(500, 100, 100, block=edge, gap=edge)

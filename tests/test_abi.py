@@ -120,10 +120,11 @@ def test_plan_degenerate_geometries():
     assert s.n_nodes == 1 and s.n_fluid == 1
     s = lbm.plan(one, propagation="aa")
     assert s.pdf_bytes >= 19 * 8
+    for prop in ("aa", "push"):
+        s = lbm.plan(one, propagation=prop, layout="aos")
+        assert s.stride == 19 and s.bytes_per_update == 305.0
     with pytest.raises(lbm.LBMError):
-        lbm.plan(one, propagation="aa", layout="aos")
-    with pytest.raises(lbm.LBMError):
-        lbm.plan(one, propagation="push", layout="aos")
+        lbm.plan(one, propagation="aa", layout="aos", addressing="list", bounce="halfway")
     m = np.zeros((8, 6, 5), dtype=np.uint8)
     pull, push = lbm.plan(m), lbm.plan(m, propagation="push")
     assert push.bytes_per_update == pull.bytes_per_update and push.pdf_bytes == pull.pdf_bytes

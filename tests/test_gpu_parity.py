@@ -79,6 +79,17 @@ def test_list_random_state(L, shape):
     assert rel_maxabs(got, ref) <= TOL
 
 
+def test_pipe_all_addressings(L):
+    """Staircase circular pipe (the pipe geometry of Sect. 2) for every
+    addressing, both bounce-back kinds on the full array."""
+    mask = I.pipe_mask(37, 18, 17)
+    for kw in ({"addressing": "list", "bounce": "halfway"}, {"addressing": "ria", "bounce": "halfway"},
+               {"addressing": "direct", "bounce": "halfway"}, {"addressing": "direct", "bounce": "fullway"},
+               {"layout": "aos", "bounce": "fullway"}):
+        got, ref, _ = _case(mask, 30, L, g=(1e-5, 0.0, 0.0), **kw)
+        assert rel_maxabs(got, ref) <= TOL, kw
+
+
 def test_spheres_list_and_direct(L):
     """Porous box of overlapping spheres, fully periodic, both addressings."""
     mask, phi, _ = I.spheres_mask(40, 36, 32, seed=1, porosity=0.5, rmin=3, rmax=6)
@@ -242,7 +253,9 @@ def test_init_fields_reports_given_state(L, kw):
 
 @pytest.mark.parametrize("kw", [{"bounce": "fullway"}, {"bounce": "halfway"},
                                 {"addressing": "list", "bounce": "halfway"},
-                                {"bounce": "fullway", "storage": "f64", "block": 64}])
+                                {"bounce": "fullway", "storage": "f64", "block": 64},
+                                {"layout": "aos", "bounce": "fullway"},
+                                {"layout": "aos", "bounce": "halfway"}])
 @pytest.mark.parametrize("steps", [24, 25])
 def test_aa_pattern_random_state(L, kw, steps):
     """AA pattern (one lattice, alternating local and neighbour kernels)
@@ -273,7 +286,9 @@ def test_aa_matches_two_lattice_bitwise_free(L):
 
 @pytest.mark.parametrize("kw", [{"bounce": "fullway"}, {"bounce": "halfway"},
                                 {"addressing": "list", "bounce": "halfway"},
-                                {"bounce": "fullway", "storage": "f64", "block": 64}])
+                                {"bounce": "fullway", "storage": "f64", "block": 64},
+                                {"layout": "aos", "bounce": "fullway"},
+                                {"layout": "aos", "bounce": "halfway"}])
 def test_push_random_state(L, kw):
     """One-step push kernels (read the node, collide, scatter to the
     neighbours) against the oracle from a random state with random solids
@@ -308,6 +323,7 @@ def test_push_and_pull_agree_stepwise(L):
 
 @pytest.mark.parametrize("kw", [{}, {"layout": "aos"}, {"bounce": "halfway"}, {"propagation": "aa"},
                                 {"propagation": "push"}, {"propagation": "push", "bounce": "halfway"},
+                                {"propagation": "aa", "layout": "aos"}, {"propagation": "push", "layout": "aos"},
                                 {"addressing": "list", "bounce": "halfway"},
                                 {"addressing": "list", "bounce": "halfway", "propagation": "push"},
                                 {"addressing": "ria", "bounce": "halfway"},
