@@ -106,7 +106,7 @@ extern "C" {
 /* ---- parameter and buffer records ------------------------------------ */
 typedef struct {
   int32_t nx, ny, nz;       /* nodes per axis, walls included; each >= 1   */
-  int32_t layout;           /* LBM_SOA | LBM_AOS (the lists require SOA)   */
+  int32_t layout;           /* LBM_SOA | LBM_AOS (LIST_RIA requires SOA)   */
   int32_t addressing;       /* LBM_DIRECT | LBM_LIST | LBM_LIST_RIA        */
   int32_t storage;          /* LBM_F64 | LBM_F32_SHIFTED | LBM_F16_SHIFTED
                                | LBM_F16_SHIFTED_SR                        */
@@ -131,11 +131,13 @@ typedef struct {
   int64_t n_nodes;          /* nx*ny*nz                                    */
   int64_t n_fluid;          /* nodes with mask == 0                        */
   int64_t n_sites;          /* nodes the sweep updates: N (direct) or Nf   */
-  int64_t stride;           /* elements between direction arrays (SOA,
-                               LIST); 19 for AOS                           */
+  int64_t stride;           /* elements between direction arrays (SOA);
+                               19 for AOS (records, also for LIST)         */
   int64_t pdf_bytes;        /* size of EACH of pdf_a and pdf_b             */
   int64_t mask_bytes;       /* device mask: N bytes                        */
-  int64_t adj_bytes;        /* LIST: 18*stride int32; else 0               */
+  int64_t adj_bytes;        /* LIST: 18 direction arrays of int32 slots
+                               (SOA: stride entries apart; AOS: Nf padded
+                               to 64); else 0                              */
   int64_t fluid_index_bytes;/* LIST, LIST_RIA: Nf int32 (list -> node)     */
   int64_t node_map_bytes;   /* LIST, LIST_RIA: N int32 (node -> list/-1)   */
   int64_t links_bytes;      /* DIRECT + HALFWAY: N uint32 link words       */
@@ -188,7 +190,7 @@ typedef struct lbm_ctx lbm_ctx;
 /* Sizes of every buffer for a parameter set and a host mask (N bytes).
  * Counts fluid nodes (and, for LIST_RIA, the runs); validates parameters
  * (tau+ > 1/2, Lambda > 0, dims >= 1 and <= 65535 on y and z, N < 2^31,
- * the lists need 19*stride < 2^31).  Allocates nothing.
+ * the lists need every population slot index below 2^31).  Allocates nothing.
  * Errors: EINVAL, EOVERFLOW. */
 int lbm_plan(const lbm_params* params, const uint8_t* mask_host, lbm_sizes* out);
 

@@ -21,7 +21,7 @@ LIB = os.path.join(OUT_DIR, "liblbm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["lbm_api.hip", "sweep.hip", "sweep_aos.hip", "sweep_aa.hip", "sweep_push.hip",
-           "sweep_ria.hip", "state_io.hip", "diagnostics.hip", "membench.hip", "nn.hip"]
+           "sweep_ria.hip", "sweep_list_aos.hip", "state_io.hip", "diagnostics.hip", "membench.hip", "nn.hip"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -14,7 +14,8 @@ namespace lbm {
 
 struct View {
   int nx, ny, nz;
-  int64_t stride;
+  int64_t stride;          // population stride (SOA) or Q (AOS)
+  int64_t adj_stride;      // list adjacency: entries between directions
   const uint8_t* mask;
   const int32_t* adj;
   const int32_t* node_map;
@@ -51,14 +52,15 @@ __device__ __forceinline__ void node_xyz(const View& v, int64_t n, int& x, int& 
 // neighbour x - c_i, else slot opp(i) of the node) unless the lattice is an
 // AA lattice after an odd number of updates (slot opp(i) of the neighbour,
 // else slot i of the node).
+template <int LAYOUT>
 __device__ __forceinline__ int64_t list_slot(const View& v, int m, int i) {
-  if (v.adj) return v.adj[(int64_t)(i - 1) * v.stride + m];
+  if (v.adj) return v.adj[(int64_t)(i - 1) * v.adj_stride + m];
   int x, y, z;
   node_xyz(v, v.fluid_index[m], x, y, z);
   const int t = v.node_map[wrap_node(v, x - Vel::cx[i], y - Vel::cy[i], z - Vel::cz[i])];
   const bool aa = v.aa == 2;
-  return t >= 0 ? (int64_t)(aa ? Vel::opp[i] : i) * v.stride + t
-                : (int64_t)(aa ? i : Vel::opp[i]) * v.stride + m;
+  return t >= 0 ? vslot<LAYOUT>(t, aa ? Vel::opp[i] : i, v.stride)
+                : vslot<LAYOUT>(m, aa ? i : Vel::opp[i], v.stride);
 }
 
 template <class ST>
@@ -89,10 +91,10 @@ __device__ __forceinline__ bool gather_canonical(const typename ST::T* __restric
   if (ADDR == LBM_LIST) {
     const int m = v.node_map[node];
     if (m < 0) return false;
-    f[0] = to_f64<ST>(src[m], 0, v);
+    f[0] = to_f64<ST>(src[vslot<LAYOUT>(m, 0, v.stride)], 0, v);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const int64_t at = v.aa == 1 ? (int64_t)i * v.stride + m : list_slot(v, m, i);
+      const int64_t at = v.aa == 1 ? vslot<LAYOUT>(m, i, v.stride) : list_slot<LAYOUT>(v, m, i);
       f[i] = to_f64<ST>(src[at], i, v);
     }
     return true;
@@ -167,12 +169,15 @@ template <int V>
 using IC = std::integral_constant<int, V>;
 
 // Call f(storage_tag, layout, addressing, bounce) with compile-time tags for
-// the parameter combination of p (both lists imply SOA and half-way and
-// share the LIST tag: node-wise access differs only inside list_slot).
+// the parameter combination of p (both lists imply half-way and share the
+// LIST tag: node-wise access differs only inside list_slot).
 template <class F>
 hipError_t dispatch(const lbm_params& p, F&& f) {
   auto by_store = [&](auto st) -> hipError_t {
-    if (p.addressing != LBM_DIRECT) return f(st, IC<LBM_SOA>{}, IC<LBM_LIST>{}, IC<LBM_HALFWAY>{});
+    if (p.addressing != LBM_DIRECT) {
+      if (p.layout == LBM_SOA) return f(st, IC<LBM_SOA>{}, IC<LBM_LIST>{}, IC<LBM_HALFWAY>{});
+      return f(st, IC<LBM_AOS>{}, IC<LBM_LIST>{}, IC<LBM_HALFWAY>{});
+    }
     if (p.layout == LBM_SOA) {
       if (p.bounce == LBM_FULLWAY) return f(st, IC<LBM_SOA>{}, IC<LBM_DIRECT>{}, IC<LBM_FULLWAY>{});
       return f(st, IC<LBM_SOA>{}, IC<LBM_DIRECT>{}, IC<LBM_HALFWAY>{});

@@ -18,6 +18,7 @@ struct lbm_ctx {
   int u_prev_valid;    // u_prev holds the velocity of a previous call
   int block;           // threads per workgroup for the sweeps
   int device;
+  int64_t adj_stride;  // LIST: entries between adjacency directions
   // LIST_RIA run tables, carved out of b.ria: run_start[n_runs + 1] (first
   // list index of each run, then n_fluid), run_adj[18][run_stride] (the
   // slot of direction i for the run's first node), chunk_run[ceil(Nf/64)]
@@ -48,6 +49,8 @@ hipError_t launch_pull(lbm_ctx* c, const void* src, void* dst);
 hipError_t launch_pull_aos(lbm_ctx* c, const void* src, void* dst);
 hipError_t launch_push(lbm_ctx* c, const void* src, void* dst);
 hipError_t launch_aa(lbm_ctx* c, void* buf);
+// Fluid list in AoS records: pull, push and both AA steps.
+hipError_t launch_list_aos(lbm_ctx* c, const void* src, void* dst);
 // Run-length list (LIST_RIA): the pull and push sweeps and the AA
 // neighbour kernel (the AA local kernel needs no addressing).
 hipError_t launch_pull_ria(lbm_ctx* c, const void* src, void* dst);

@@ -53,8 +53,12 @@ static int validate(const lbm_params* p) {
   }
   if (p->storage < LBM_F64 || p->storage > LBM_F16_SHIFTED_SR) { set_error("bad storage"); return LBM_EINVAL; }
   if (p->bounce != LBM_FULLWAY && p->bounce != LBM_HALFWAY) { set_error("bad bounce"); return LBM_EINVAL; }
-  if (is_list(*p) && (p->layout != LBM_SOA || p->bounce != LBM_HALFWAY)) {
-    set_error("list addressing requires SOA layout and half-way bounce-back");
+  if (is_list(*p) && p->bounce != LBM_HALFWAY) {
+    set_error("list addressing requires half-way bounce-back");
+    return LBM_EINVAL;
+  }
+  if (p->addressing == LBM_LIST_RIA && p->layout != LBM_SOA) {
+    set_error("the run-length list requires the SOA layout");
     return LBM_EINVAL;
   }
   if ((p->storage == LBM_F16_SHIFTED || p->storage == LBM_F16_SHIFTED_SR) &&
@@ -128,6 +132,12 @@ static int64_t find_runs(const lbm_params* p, const uint8_t* mask, uint8_t* is_s
   return runs;
 }
 
+// Entries between the direction arrays of the list adjacency: the population
+// stride for SOA, the fluid count padded to 64 for AOS records.
+static int64_t list_adj_stride(const lbm_params* p, const lbm_sizes* s) {
+  return p->layout == LBM_AOS ? round_up(s->n_sites < 1 ? 1 : s->n_sites, 64) : s->stride;
+}
+
 static int plan_sizes(const lbm_params* p, int64_t n_fluid, int64_t n_runs, lbm_sizes* s) {
   const int64_t N = (int64_t)p->nx * p->ny * p->nz;
   if (N >= 0x7fffffffLL) { set_error("lattice of %lld nodes exceeds 32-bit node indices", (long long)N); return LBM_EOVERFLOW; }
@@ -138,7 +148,7 @@ static int plan_sizes(const lbm_params* p, int64_t n_fluid, int64_t n_runs, lbm_
   s->n_sites = is_list(*p) ? n_fluid : N;
   if (p->layout == LBM_AOS) {
     s->stride = Q;
-    s->pdf_bytes = round_up(N * Q * es, 256);
+    s->pdf_bytes = round_up((s->n_sites < 1 ? 1 : s->n_sites) * Q * es, 256);
   } else {
     // Direction arrays start on 256-byte boundaries.  The automatic pad
     // shifts consecutive arrays by 1 KiB when their natural spacing is a
@@ -153,11 +163,12 @@ static int plan_sizes(const lbm_params* p, int64_t n_fluid, int64_t n_runs, lbm_
   }
   s->mask_bytes = round_up(N, 256);
   if (is_list(*p)) {
-    if (s->stride * Q >= 0x7fffffffLL) {
+    const int64_t slots = p->layout == LBM_AOS ? s->n_sites * Q : s->stride * Q;
+    if (slots >= 0x7fffffffLL) {
       set_error("list of %lld fluid nodes overflows int32 adjacency entries", (long long)n_fluid);
       return LBM_EOVERFLOW;
     }
-    if (p->addressing == LBM_LIST) s->adj_bytes = round_up(s->stride * (Q - 1) * 4, 256);
+    if (p->addressing == LBM_LIST) s->adj_bytes = round_up(list_adj_stride(p, s) * (Q - 1) * 4, 256);
     s->fluid_index_bytes = round_up((n_fluid < 1 ? 1 : n_fluid) * 4, 256);
     s->node_map_bytes = round_up(N * 4, 256);
   }
@@ -289,6 +300,7 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
   }
   if (!ria) c->b.ria = nullptr;
   c->n_runs = runs;
+  c->adj_stride = list_adj_stride(params, &s);
   if (ria) {
     const RiaLayout L = ria_layout(runs, s.n_fluid);
     char* base = (char*)c->b.ria;
@@ -417,8 +429,9 @@ int lbm_step(lbm_ctx* c, int32_t n) {
   if (!c || n < 0) { set_error("bad ctx or negative step count"); return LBM_EINVAL; }
   LBM_HIP(hipSetDevice(c->device), "hipSetDevice");
   for (int32_t k = 0; k < n; ++k) {
+    const bool list_aos = is_list(c->p) && c->p.layout == LBM_AOS;
     if (c->p.propagation == LBM_AA) {
-      hipError_t e = launch_aa(c, pdf_buf(c, 0));
+      hipError_t e = list_aos ? launch_list_aos(c, pdf_buf(c, 0), nullptr) : launch_aa(c, pdf_buf(c, 0));
       if (e != hipSuccess) return hip_fail(e, "AA sweep launch");
       c->aa_odd = 1 - c->aa_odd;
     } else {
@@ -426,7 +439,8 @@ int lbm_step(lbm_ctx* c, int32_t n) {
       void* dst = pdf_buf(c, 1 - c->cur);
       const bool ria = c->p.addressing == LBM_LIST_RIA;
       hipError_t e;
-      if (c->p.propagation == LBM_OS_PUSH) e = ria ? launch_push_ria(c, src, dst) : launch_push(c, src, dst);
+      if (list_aos) e = launch_list_aos(c, src, dst);
+      else if (c->p.propagation == LBM_OS_PUSH) e = ria ? launch_push_ria(c, src, dst) : launch_push(c, src, dst);
       else if (ria) e = launch_pull_ria(c, src, dst);
       else if (c->p.layout == LBM_AOS) e = launch_pull_aos(c, src, dst);
       else e = launch_pull(c, src, dst);

@@ -12,6 +12,7 @@ static View make_view(const lbm_ctx* c) {
   v.ny = c->p.ny;
   v.nz = c->p.nz;
   v.stride = c->s.stride;
+  v.adj_stride = c->adj_stride;
   v.mask = c->b.mask;
   v.adj = c->b.adj;
   v.node_map = c->b.node_map;
@@ -61,7 +62,8 @@ hipError_t launch_fill_rest(lbm_ctx* c, void* buf) {
 // slot opp(i)*stride + m when the neighbour is solid (half-way bounce-back).
 // For the AA pattern the neighbour kernel reads the reversed slots instead:
 // opp(i)*stride + map(x - c_i), or i*stride + m at a solid neighbour.
-__device__ __forceinline__ void adjacency_of(const View& v, int m, int aa, int32_t* out,
+// Slots are layout-dependent: direction-major (SOA) or record-major (AOS).
+__device__ __forceinline__ void adjacency_of(const View& v, int m, int aa, bool aos, int32_t* out,
                                              int64_t out_stride) {
   int x, y, z;
   node_xyz(v, v.fluid_index[m], x, y, z);
@@ -71,22 +73,25 @@ __device__ __forceinline__ void adjacency_of(const View& v, int m, int aa, int32
     const int t = v.node_map[sn];
     const int dn = aa ? Vel::opp[i] : i;     // direction slot at the neighbour
     const int ds = aa ? i : Vel::opp[i];     // direction slot at the node itself
-    const int64_t s = t >= 0 ? (int64_t)dn * v.stride + t : (int64_t)ds * v.stride + m;
+    const int64_t node = t >= 0 ? t : m;
+    const int d = t >= 0 ? dn : ds;
+    const int64_t s = aos ? node * Q + d : (int64_t)d * v.stride + node;
     out[(int64_t)(i - 1) * out_stride] = (int32_t)s;
   }
 }
 
-__global__ void k_build_adjacency(View v, int nf, int aa, int32_t* __restrict__ adj) {
+__global__ void k_build_adjacency(View v, int nf, int aa, int aos, int32_t* __restrict__ adj) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= nf) return;
-  adjacency_of(v, m, aa, adj + m, v.stride);
+  adjacency_of(v, m, aa, aos != 0, adj + m, v.adj_stride);
 }
 
 hipError_t launch_build_adjacency(lbm_ctx* c) {
   const int nf = (int)c->s.n_fluid;
   if (nf == 0) return hipSuccess;
   hipLaunchKernelGGL(k_build_adjacency, dim3(grid_for(nf, 256)), dim3(256), 0, c->stream,
-                     make_view(c), nf, c->p.propagation == LBM_OS ? 0 : 1, c->b.adj);
+                     make_view(c), nf, c->p.propagation == LBM_OS ? 0 : 1, c->p.layout == LBM_AOS ? 1 : 0,
+                     c->b.adj);
   return hipGetLastError();
 }
 
@@ -96,7 +101,7 @@ __global__ void k_build_run_adj(View v, const int32_t* __restrict__ run_start, i
                                 int aa, int64_t run_stride, int32_t* __restrict__ run_adj) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_runs) return;
-  adjacency_of(v, run_start[r], aa, run_adj + r, run_stride);
+  adjacency_of(v, run_start[r], aa, false, run_adj + r, run_stride);
 }
 
 hipError_t launch_build_run_adj(lbm_ctx* c) {

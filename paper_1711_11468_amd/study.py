@@ -29,6 +29,7 @@ FORMS = [
     ("os-push-soa", dict(propagation="push")),
     ("list-os-pull-soa", dict(addressing="list", bounce="halfway")),
     ("list-os-push-soa", dict(addressing="list", bounce="halfway", propagation="push")),
+    ("list-os-pull-aos", dict(addressing="list", bounce="halfway", layout="aos")),
     ("list-ria-os-pull-soa", dict(addressing="ria", bounce="halfway")),
     ("aa-soa", dict(propagation="aa")),
     ("list-aa-soa", dict(addressing="list", bounce="halfway", propagation="aa")),
@@ -74,7 +75,7 @@ def main(argv=None):
             name, r["mflups"], r["gbs"], r["bytes_per_fluid_update"]), flush=True)
     pipe = I.pipe_mask(500, 100, 100)
     for name, kw in FORMS:
-        if name == "os-pull-aos":
+        if name in ("os-pull-aos", "list-os-pull-aos"):
             continue
         r = time_form(pipe, args.steps, args.warmup, **kw)
         res["pipe_500x100x100"][name] = r
@@ -84,7 +85,7 @@ def main(argv=None):
         m = I.blocks_mask(500, 100, 100, block=edge, gap=edge)
         row = {"block": edge, "gap": edge, "fluid_fraction": float((m == 0).mean())}
         for name, kw in FORMS:
-            if name in ("os-pull-aos",):
+            if name in ("os-pull-aos", "list-os-pull-aos"):
                 continue
             row[name] = time_form(m, args.steps, args.warmup, **kw)
         res["blocks_500x100x100"].append(row)

@@ -73,7 +73,7 @@ def test_byte_model_matches_table1():
     assert lst + write_allocate == rows["os-list"]
 
 
-@pytest.mark.parametrize("kw", [dict(tau_plus=0.5), dict(magic=0.0), dict(layout="aos", addressing="list", bounce="halfway"),
+@pytest.mark.parametrize("kw", [dict(tau_plus=0.5), dict(magic=0.0), dict(layout="aos", addressing="ria", bounce="halfway"),
                                 dict(addressing="list", bounce="fullway"), dict(block=96),
                                 dict(storage="f16s", f16_scale_log2=30), dict(pad=-2)])
 def test_plan_rejects_bad_parameters(kw):
@@ -123,8 +123,8 @@ def test_plan_degenerate_geometries():
     for prop in ("aa", "push"):
         s = lbm.plan(one, propagation=prop, layout="aos")
         assert s.stride == 19 and s.bytes_per_update == 305.0
-    with pytest.raises(lbm.LBMError):
-        lbm.plan(one, propagation="aa", layout="aos", addressing="list", bounce="halfway")
+    s = lbm.plan(one, propagation="aa", layout="aos", addressing="list", bounce="halfway")
+    assert s.stride == 19 and s.adj_bytes >= 18 * 64 * 4
     m = np.zeros((8, 6, 5), dtype=np.uint8)
     pull, push = lbm.plan(m), lbm.plan(m, propagation="push")
     assert push.bytes_per_update == pull.bytes_per_update and push.pdf_bytes == pull.pdf_bytes
@@ -193,6 +193,14 @@ def test_ria_runs(which):
         nf = s.n_fluid
         expect = 304 + 1 + 4 / 64 + 4 * 19 * s.n_runs / nf
         assert abs(s.bytes_per_update - expect) < 1e-9
+
+
+def test_list_aos_sizes():
+    m = I.random_solid_mask(20, 9, 7, seed=1, fraction=0.3)
+    s = lbm.plan(m, layout="aos", addressing="list", bounce="halfway")
+    nf = int((m == 0).sum())
+    assert s.n_sites == nf and s.stride == 19 and s.pdf_bytes >= nf * 19 * 8
+    assert s.adj_bytes >= 18 * nf * 4 and s.bytes_per_update == 376.0
 
 
 def test_ria_validation():

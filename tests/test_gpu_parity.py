@@ -68,12 +68,13 @@ def test_direct_random_state(L, layout, bounce, shape):
     assert rel_maxabs(got, ref) <= TOL
 
 
+@pytest.mark.parametrize("layout", ["soa", "aos"])
 @pytest.mark.parametrize("shape", [(9, 10, 12), (6, 9, 70)])
-def test_list_random_state(L, shape):
+def test_list_random_state(L, shape, layout):
     nz, ny, nx = shape
     mask = I.random_solid_mask(nx, ny, nz, seed=5, fraction=0.3)
     f0 = random_state(mask, seed=4, amplitude=0.02, bounce="halfway")
-    got, ref, lat = _case(mask, 25, L, f0=f0, addressing="list", bounce="halfway",
+    got, ref, lat = _case(mask, 25, L, f0=f0, addressing="list", bounce="halfway", layout=layout,
                           g=(-3e-5, 1e-4, 2e-5), tau_plus=1.1, magic=1 / 12)
     assert lat.n_fluid == int((mask == 0).sum())
     assert rel_maxabs(got, ref) <= TOL
@@ -85,7 +86,8 @@ def test_pipe_all_addressings(L):
     mask = I.pipe_mask(37, 18, 17)
     for kw in ({"addressing": "list", "bounce": "halfway"}, {"addressing": "ria", "bounce": "halfway"},
                {"addressing": "direct", "bounce": "halfway"}, {"addressing": "direct", "bounce": "fullway"},
-               {"layout": "aos", "bounce": "fullway"}):
+               {"layout": "aos", "bounce": "fullway"},
+               {"layout": "aos", "addressing": "list", "bounce": "halfway"}):
         got, ref, _ = _case(mask, 30, L, g=(1e-5, 0.0, 0.0), **kw)
         assert rel_maxabs(got, ref) <= TOL, kw
 
@@ -105,7 +107,8 @@ def test_import_export_roundtrip(L):
     mask = I.random_solid_mask(11, 7, 6, seed=8, fraction=0.25)
     for kw in ({"layout": "soa", "bounce": "fullway"}, {"layout": "aos", "bounce": "halfway"},
                {"addressing": "list", "bounce": "halfway"}, {"addressing": "ria", "bounce": "halfway"},
-               {"addressing": "ria", "bounce": "halfway", "propagation": "aa"}):
+               {"addressing": "ria", "bounce": "halfway", "propagation": "aa"},
+               {"addressing": "list", "bounce": "halfway", "layout": "aos"}):
         f0 = random_state(mask, seed=1, amplitude=0.05, bounce=kw["bounce"])
         lat = L.Lattice(mask, **kw)
         lat.import_(f0)
@@ -126,12 +129,13 @@ def test_block_size_bitwise_and_layouts_agree(L):
         return lat.export()
 
     for base, blocks in (({}, (64, 128, 256, 1024)), ({"layout": "aos"}, (64, 256, 512)),
-                         ({"addressing": "list"}, (64, 256, 1024))):
+                         ({"addressing": "list"}, (64, 256, 1024)),
+                         ({"addressing": "list", "layout": "aos"}, (64, 256, 512))):
         outs = [run(block=b, **base) for b in blocks]
         for o in outs[1:]:
             assert np.array_equal(o, outs[0]), base
     ref = run()
-    for kw in ({"layout": "aos"}, {"addressing": "list"}):
+    for kw in ({"layout": "aos"}, {"addressing": "list"}, {"addressing": "list", "layout": "aos"}):
         assert rel_maxabs(run(**kw), ref) <= 1e-15, kw
 
 
@@ -255,7 +259,8 @@ def test_init_fields_reports_given_state(L, kw):
                                 {"addressing": "list", "bounce": "halfway"},
                                 {"bounce": "fullway", "storage": "f64", "block": 64},
                                 {"layout": "aos", "bounce": "fullway"},
-                                {"layout": "aos", "bounce": "halfway"}])
+                                {"layout": "aos", "bounce": "halfway"},
+                                {"layout": "aos", "addressing": "list", "bounce": "halfway"}])
 @pytest.mark.parametrize("steps", [24, 25])
 def test_aa_pattern_random_state(L, kw, steps):
     """AA pattern (one lattice, alternating local and neighbour kernels)
@@ -288,7 +293,8 @@ def test_aa_matches_two_lattice_bitwise_free(L):
                                 {"addressing": "list", "bounce": "halfway"},
                                 {"bounce": "fullway", "storage": "f64", "block": 64},
                                 {"layout": "aos", "bounce": "fullway"},
-                                {"layout": "aos", "bounce": "halfway"}])
+                                {"layout": "aos", "bounce": "halfway"},
+                                {"layout": "aos", "addressing": "list", "bounce": "halfway"}])
 def test_push_random_state(L, kw):
     """One-step push kernels (read the node, collide, scatter to the
     neighbours) against the oracle from a random state with random solids
@@ -327,7 +333,9 @@ def test_push_and_pull_agree_stepwise(L):
                                 {"addressing": "list", "bounce": "halfway"},
                                 {"addressing": "list", "bounce": "halfway", "propagation": "push"},
                                 {"addressing": "ria", "bounce": "halfway"},
-                                {"addressing": "ria", "bounce": "halfway", "propagation": "aa"}])
+                                {"addressing": "ria", "bounce": "halfway", "propagation": "aa"},
+                                {"addressing": "list", "bounce": "halfway", "layout": "aos"},
+                                {"addressing": "list", "bounce": "halfway", "layout": "aos", "propagation": "aa"}])
 def test_degenerate_lattices(L, kw):
     """1-node and thin lattices (every neighbour is the node itself or a
     wrap-around), and a geometry without fluid, behave like the oracle."""
