@@ -163,73 +163,127 @@ __global__ void k_transpose_w(const uint16_t* __restrict__ w, uint16_t* __restri
 }
 
 // ---- weight gradient ------------------------------------------------------
-// Grid (chunks, taps); each block sums its chunk of output voxels for one
-// tap into all (c_out x c_in) 16x16 tiles, staging dy and the tap-shifted
-// input transposed ([channel][voxel]) in LDS.
+// dW[tap][co][ci] = sum over output voxels p of dy[p][co] x[in(p, tap)][ci]:
+// a GEMM whose K dimension is the voxel.  Grid (chunks, tap groups); a block
+// owns a chunk of output voxels and a group of TPB taps.  Per 64-voxel step
+// it stages dy once and the tap-shifted input of every tap of its group
+// (16-byte loads, channels-last), both transposed to [channel][voxel] in LDS
+// so each MFMA operand is one 8-byte LDS read; the TPB x (co/16) x (ci/16)
+// output tiles are spread over the four wavefronts (at most TPW each).
+constexpr int kWgRow = 68;  // LDS row: 64 voxels + 4 pad (8-byte aligned, fewer bank conflicts)
+
+// Transposed store of four voxels x eight bf16 channels: row j of dst (rows
+// kWgRow apart) receives channel j of voxels 0..3 as one 8-byte word.
+__device__ __forceinline__ void store_t4(uint16_t* dst, const uint4 (&v)[4]) {
+  const uint32_t w[4][4] = {{v[0].x, v[0].y, v[0].z, v[0].w}, {v[1].x, v[1].y, v[1].z, v[1].w},
+                            {v[2].x, v[2].y, v[2].z, v[2].w}, {v[3].x, v[3].y, v[3].z, v[3].w}};
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int h = j >> 1, sh = (j & 1) * 16;
+    uint2 o;
+    o.x = ((w[0][h] >> sh) & 0xffffu) | (((w[1][h] >> sh) & 0xffffu) << 16);
+    o.y = ((w[2][h] >> sh) & 0xffffu) | (((w[3][h] >> sh) & 0xffffu) << 16);
+    *(uint2*)(dst + j * kWgRow) = o;
+  }
+}
+static_assert(kWgRow % 4 == 0, "8-byte aligned operand rows");
+
 template <int STRIDE, int TAPS, int TPW>
 __global__ void __launch_bounds__(256)
 k_conv_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dyp,
-             float* __restrict__ partial, int64_t chunk, Geom g) {
-  __shared__ __align__(16) uint16_t dyT[128 * 64];
-  __shared__ __align__(16) uint16_t xT[128 * 64];
+             float* __restrict__ partial, int64_t chunk, int tpb, Geom g) {
+  extern __shared__ __align__(16) uint16_t wg_lds[];
+  __shared__ int vb[64][4];
+  uint16_t* dyT = wg_lds;                   // [co][kWgRow]
+  uint16_t* xT = wg_lds + g.co * kWgRow;    // [tpb][ci][kWgRow]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tap = blockIdx.y;
-  int dz, dy, dx;
-  tap_offsets(tap, TAPS, dz, dy, dx);
+  const int tap0 = blockIdx.y * tpb;
   const int64_t start = (int64_t)blockIdx.x * chunk;
   int64_t end = start + chunk;
   if (end > g.m_out) end = g.m_out;
-  const int nbo = g.co / 16, nbi = g.ci / 16, ntiles = nbo * nbi;
+  const int nbi = g.ci / 16, nt = (g.co / 16) * nbi, ntiles = tpb * nt;
+  const int cvo = g.co / 8, cvi = g.ci / 8;
   const int row = lane & 15, kq = lane >> 4;
   f4 acc[TPW];
+  int aoff[TPW], boff[TPW];  // LDS element offsets of this lane's operands, per tile
 #pragma unroll
-  for (int j = 0; j < TPW; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int j = 0; j < TPW; ++j) {
+    acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+    const int tile = wave + 4 * j;
+    const int tl = tile / nt, t2 = tile - tl * nt;
+    const int mo = t2 / nbi, ni = t2 - mo * nbi;
+    aoff[j] = (mo * 16 + row) * kWgRow + 4 * kq;
+    boff[j] = (tl * g.ci + ni * 16 + row) * kWgRow + 4 * kq;
+  }
   for (int64_t p0 = start; p0 < end; p0 += 64) {
-    __syncthreads();
-    for (int e = tid; e < 64 * g.co; e += 256) {
-      const int p = e / g.co, c = e - p * g.co;
-      const int64_t vox = p0 + p;
-      dyT[c * 64 + p] = vox < end ? dyp[vox * g.co + c] : (uint16_t)0;
-    }
-    for (int e = tid; e < 64 * g.ci; e += 256) {
-      const int p = e / g.ci, c = e - p * g.ci;
-      const int64_t vox = p0 + p;
-      uint16_t val = 0;
+    __syncthreads();  // the previous step's operands are consumed
+    if (tid < 64) {
+      const int64_t vox = p0 + tid;
       if (vox < end) {
         int64_t t = vox;
-        const int xo = (int)(t % g.Wo);
+        vb[tid][3] = (int)(t % g.Wo);
         t /= g.Wo;
-        const int yo = (int)(t % g.Ho);
+        vb[tid][2] = (int)(t % g.Ho);
         t /= g.Ho;
-        const int zo = (int)(t % g.Do);
-        const int b = (int)(t / g.Do);
-        const int zi = wrapi(STRIDE * zo + dz, g.D), yi = wrapi(STRIDE * yo + dy, g.H),
-                  xi = wrapi(STRIDE * xo + dx, g.W);
-        val = x[((((int64_t)b * g.D + zi) * g.H + yi) * g.W + xi) * g.ci + c];
+        vb[tid][1] = (int)(t % g.Do);
+        vb[tid][0] = (int)(t / g.Do);
+      } else {
+        vb[tid][0] = -1;
       }
-      xT[c * 64 + p] = val;
+    }
+    // dy: items of 4 voxels x 8 channels; four 16-byte loads become eight
+    // 8-byte LDS rows (one channel, four voxels each)
+    for (int e = tid; e < 16 * cvo; e += 256) {
+      const int p4 = e / cvo, cv = e - p4 * cvo;
+      const int64_t vox = p0 + 4 * p4;
+      uint4 v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        v[k] = vox < end ? *(const uint4*)(dyp + (vox + k) * g.co + cv * 8) : make_uint4(0u, 0u, 0u, 0u);
+      store_t4(dyT + (cv * 8) * kWgRow + 4 * p4, v);
+    }
+    __syncthreads();  // voxel coordinates ready
+    // input of each tap of the group, same items (an item's voxels may lie
+    // in different grid rows when rows are short)
+    for (int e = tid; e < tpb * 16 * cvi; e += 256) {
+      const int tl = e / (16 * cvi);
+      const int r = e - tl * 16 * cvi;
+      const int p4 = r / cvi, cv = r - p4 * cvi;
+      int dz, dy, dx;
+      tap_offsets(tap0 + tl, TAPS, dz, dy, dx);
+      uint4 v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int* c = vb[4 * p4 + k];
+        v[k] = make_uint4(0u, 0u, 0u, 0u);
+        if (c[0] >= 0) {
+          const int zi = wrapi(STRIDE * c[1] + dz, g.D), yi = wrapi(STRIDE * c[2] + dy, g.H),
+                    xi = wrapi(STRIDE * c[3] + dx, g.W);
+          v[k] = *(const uint4*)(x + ((((int64_t)c[0] * g.D + zi) * g.H + yi) * g.W + xi) * g.ci + cv * 8);
+        }
+      }
+      store_t4(xT + (tl * g.ci + cv * 8) * kWgRow + 4 * p4, v);
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
+    for (int j = 0; j < TPW; ++j) {
+      if (wave + 4 * j < ntiles) {
 #pragma unroll
-      for (int j = 0; j < TPW; ++j) {
-        const int tile = wave + 4 * j;
-        if (tile < ntiles) {
-          const int mo = tile / nbi, ni = tile - mo * nbi;
-          const s4 a = *(const s4*)(&dyT[(mo * 16 + row) * 64 + kk * 16 + 4 * kq]);
-          const s4 bv = *(const s4*)(&xT[(ni * 16 + row) * 64 + kk * 16 + 4 * kq]);
+        for (int kk = 0; kk < 4; ++kk) {
+          const s4 a = *(const s4*)(&dyT[aoff[j] + kk * 16]);
+          const s4 bv = *(const s4*)(&xT[boff[j] + kk * 16]);
           acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[j], 0, 0, 0);
         }
       }
     }
   }
-  float* out = partial + ((int64_t)blockIdx.x * TAPS + tap) * g.co * g.ci;
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     const int tile = wave + 4 * j;
     if (tile < ntiles) {
-      const int mo = tile / nbi, ni = tile - mo * nbi;
+      const int tl = tile / nt, t2 = tile - tl * nt;
+      const int mo = t2 / nbi, ni = t2 - mo * nbi;
+      float* out = partial + ((int64_t)blockIdx.x * TAPS + tap0 + tl) * g.co * g.ci;
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         out[(mo * 16 + 4 * kq + r) * g.ci + ni * 16 + row] = acc[j][r];
@@ -237,7 +291,22 @@ k_conv_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dyp,
   }
 }
 
-// Sum chunk partials in chunk order.
+// Sum chunk partials in a fixed order, in two passes: segments of kSegLen
+// consecutive chunks (grid y = segment), then the segment sums in order.
+constexpr int kSegLen = 16;
+
+__global__ void k_sum_segments(const float* __restrict__ partial, float* __restrict__ seg,
+                               int64_t n, int64_t chunks) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t c0 = (int64_t)blockIdx.y * kSegLen;
+  int64_t c1 = c0 + kSegLen;
+  if (c1 > chunks) c1 = chunks;
+  float s = 0.f;
+  for (int64_t c = c0; c < c1; ++c) s += partial[c * n + i];
+  seg[(int64_t)blockIdx.y * n + i] = s;
+}
+
 __global__ void k_sum_chunks(const float* __restrict__ partial, float* __restrict__ out,
                              int64_t n, int64_t chunks) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -475,9 +544,37 @@ static Geom make_geom(const nn_conv_desc* d) {
   return g;
 }
 
-static int64_t wgrad_chunk(const Geom& g, int64_t* chunks) {
-  int64_t c = (g.m_out + 1023) / 1024;
-  if (c > 256) c = 256;
+// Tap group and tiles per wave of the weight-gradient launch: the largest
+// group (27, 9, 3 or 1 taps) whose tiles fit 14 per wave and whose staged
+// operands fit 64 KiB of LDS.
+static void wgrad_plan(const nn_conv_desc* d, int* tpb, int* tpw, size_t* lds) {
+  const int nt = (d->c_out / 16) * (d->c_in / 16);
+  const int cands[4] = {27, 9, 3, 1};
+  int best = 1;
+  for (int k = 0; k < 4; ++k) {
+    const int t = cands[k];
+    if (d->taps % t) continue;
+    const size_t bytes = (size_t)(d->c_out + t * d->c_in) * kWgRow * 2;
+    if (t * nt <= 56 && bytes <= 65536) { best = t; break; }
+  }
+  *tpb = best;
+  *tpw = (best * nt + 3) / 4;
+  *lds = (size_t)(d->c_out + best * d->c_in) * kWgRow * 2;
+}
+
+// Voxel chunks of the weight gradient (a multiple of 64 voxels each): about
+// 2048 blocks over chunks and tap groups, with the per-chunk partials
+// (taps x co x ci floats each) kept under 64 MiB.
+static int64_t wgrad_chunk(const nn_conv_desc* d, const Geom& g, int64_t* chunks) {
+  int tpb, tpw;
+  size_t lds;
+  wgrad_plan(d, &tpb, &tpw, &lds);
+  const int groups = d->taps / tpb;
+  int64_t c = (2048 + groups - 1) / groups;
+  const int64_t per_chunk_bytes = (int64_t)d->taps * d->c_out * d->c_in * 4;
+  const int64_t cap = (int64_t)64 * 1024 * 1024 / per_chunk_bytes;
+  if (c > cap) c = cap;
+  if (c > (g.m_out + 63) / 64) c = (g.m_out + 63) / 64;
   if (c < 1) c = 1;
   int64_t per = (g.m_out + c - 1) / c;
   per = (per + 63) / 64 * 64;
@@ -510,13 +607,18 @@ static void launch_dgrad_nb(int nb, const uint16_t* dy, const uint16_t* wt, floa
 }
 
 template <int STRIDE, int TAPS>
-static void launch_wgrad_tpw(int tpw, const uint16_t* x, const uint16_t* dy, float* partial,
-                             int64_t chunk, int64_t chunks, const Geom& g, hipStream_t s) {
-  const dim3 grid((unsigned)chunks, TAPS), block(256);
-  switch (tpw) {
-#define CASE(N) \
-  case N: hipLaunchKernelGGL((k_conv_wgrad<STRIDE, TAPS, N>), grid, block, 0, s, x, dy, partial, chunk, g); break;
-    CASE(1) CASE(2) CASE(4) CASE(8)
+static void launch_wgrad_tpw(int tpw, int tpb, size_t lds, const uint16_t* x, const uint16_t* dy,
+                             float* partial, int64_t chunk, int64_t chunks, const Geom& g,
+                             hipStream_t s) {
+  const dim3 grid((unsigned)chunks, TAPS / tpb), block(256);
+  const int t = tpw <= 2 ? 2 : (tpw <= 4 ? 4 : (tpw <= 8 ? 8 : 14));
+  switch (t) {
+#define CASE(N)                                                                                   \
+  case N:                                                                                         \
+    hipLaunchKernelGGL((k_conv_wgrad<STRIDE, TAPS, N>), grid, block, lds, s, x, dy, partial, chunk, \
+                       tpb, g);                                                                   \
+    break;
+    CASE(2) CASE(4) CASE(8) CASE(14)
 #undef CASE
   }
 }
@@ -581,8 +683,10 @@ int64_t nn_conv3d_wgrad_workspace(const nn_conv_desc* d) {
   if (check_desc(d)) return -1;
   const Geom g = make_geom(d);
   int64_t chunks;
-  wgrad_chunk(g, &chunks);
-  return (chunks * d->taps * d->c_out * d->c_in + chunks * d->c_out) * (int64_t)sizeof(float);
+  wgrad_chunk(d, g, &chunks);
+  const int64_t segs = (chunks + kSegLen - 1) / kSegLen;
+  return ((chunks + segs) * d->taps * d->c_out * d->c_in + (chunks + segs) * d->c_out) *
+         (int64_t)sizeof(float);
 }
 
 int nn_conv3d_wgrad(const nn_conv_desc* d, const uint16_t* x, const uint16_t* dy, float* dw,
@@ -592,20 +696,29 @@ int nn_conv3d_wgrad(const nn_conv_desc* d, const uint16_t* x, const uint16_t* dy
   const Geom g = make_geom(d);
   hipStream_t s = (hipStream_t)stream;
   int64_t chunks;
-  const int64_t chunk = wgrad_chunk(g, &chunks);
-  const int ntiles = (d->c_out / 16) * (d->c_in / 16);
-  int tpw = (ntiles + 3) / 4;
-  tpw = tpw <= 1 ? 1 : (tpw <= 2 ? 2 : (tpw <= 4 ? 4 : 8));
-  if (d->taps == 1) launch_wgrad_tpw<1, 1>(tpw, x, dy, workspace, chunk, chunks, g, s);
-  else if (d->stride == 1) launch_wgrad_tpw<1, 27>(tpw, x, dy, workspace, chunk, chunks, g, s);
-  else launch_wgrad_tpw<2, 27>(tpw, x, dy, workspace, chunk, chunks, g, s);
+  const int64_t chunk = wgrad_chunk(d, g, &chunks);
+  int tpb, tpw;
+  size_t lds;
+  wgrad_plan(d, &tpb, &tpw, &lds);
+  if (d->taps == 1) launch_wgrad_tpw<1, 1>(tpw, tpb, lds, x, dy, workspace, chunk, chunks, g, s);
+  else if (d->stride == 1) launch_wgrad_tpw<1, 27>(tpw, tpb, lds, x, dy, workspace, chunk, chunks, g, s);
+  else launch_wgrad_tpw<2, 27>(tpw, tpb, lds, x, dy, workspace, chunk, chunks, g, s);
   const int64_t nw = (int64_t)d->taps * d->c_out * d->c_in;
-  hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(nw, 256)), dim3(256), 0, s, workspace, dw, nw, chunks);
+  const int64_t segs = (chunks + kSegLen - 1) / kSegLen;
+  // workspace: [chunks][nw] partials, [segs][nw] segment sums, then the
+  // same two areas for the bias (co each)
+  float* wseg = workspace + chunks * nw;
+  hipLaunchKernelGGL(k_sum_segments, dim3(nblk(nw, 256), (unsigned)segs), dim3(256), 0, s, workspace,
+                     wseg, nw, chunks);
+  hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(nw, 256)), dim3(256), 0, s, wseg, dw, nw, segs);
   if (db) {
-    float* bpart = workspace + chunks * nw;
+    float* bpart = wseg + segs * nw;
+    float* bseg = bpart + chunks * d->c_out;
     hipLaunchKernelGGL(k_bias_partial, dim3((unsigned)chunks), dim3(256), 0, s, dy, bpart, chunk,
                        g.m_out, d->c_out);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, s, bpart, db, (int64_t)d->c_out, chunks);
+    hipLaunchKernelGGL(k_sum_segments, dim3(1, (unsigned)segs), dim3(256), 0, s, bpart, bseg,
+                       (int64_t)d->c_out, chunks);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, s, bseg, db, (int64_t)d->c_out, segs);
   }
   NN_HIP_CHECK("conv wgrad");
   return 0;

@@ -125,7 +125,10 @@ def test_unet_forward_backward_vs_reference(NN):
 
 
 def test_training_reduces_loss(NN):
-    """A few hundred Adam steps on a fixed batch drive the loss down."""
+    """A few hundred Adam steps on a fixed batch drive the loss down.  The
+    learning rate sits well inside the stable range: at 1e-3 this problem
+    is at the edge of stability and whether it settles depends on the
+    summation order of the weight gradients (equal to 1e-7)."""
     from paper_1711_11468_amd.surrogate import UNet
     dev = torch.device("cuda")
     B, n = 2, 16
@@ -139,7 +142,7 @@ def test_training_reduces_loss(NN):
     t = tgt.reshape(-1).to(dev)
     first = None
     for it in range(300):
-        loss = net.train_step(mask, t, B, n, lr=1e-3)
+        loss = net.train_step(mask, t, B, n, lr=3e-4)
         if it == 0:
             first = loss.item()
     last = loss.item()
