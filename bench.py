@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MFLUP/s + % HBM roofline; time-to-steady-state, surrogate warm vs cold"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 PHYS = dict(tau_plus=0.8, magic=3.0 / 16.0, g=(1e-6, 0.0, 0.0))
 
 
@@ -138,6 +139,45 @@ def warm_vs_cold(n=128, seeds=(100000, 100001, 100002)):
             "prediction_rel_l2_median": float(np.median([r["prediction_rel_l2"] for r in rows]))}
 
 
+def cnn_throughput(steps=10):
+    """The warm-start network's BF16 MFMA convolutions: inference on one
+    128^3 box and a training step on four 64^3 boxes (random weights and
+    inputs; the work does not depend on the values), timed with HIP events
+    on torch's current stream, where the network kernels run."""
+    import torch
+    from paper_1711_11468_amd.surrogate import UNet
+    dev = torch.device("cuda")
+    net = UNet(device=dev, seed=0)
+    g = torch.Generator().manual_seed(0)
+    out = {}
+    for key, (B, n, train) in (("infer_128", (1, 128, False)), ("train_64x4", (4, 64, True))):
+        mask = (torch.rand(B * n ** 3, generator=g) < 0.4).to(torch.uint8).to(dev)
+        tgt = torch.randn(B * n ** 3 * 3, generator=g).to(dev)
+
+        def once():
+            if train:
+                net.train_step(mask, tgt, B, n, lr=1e-4)
+            else:
+                net.forward(mask, B, n)
+        for _ in range(3):
+            once()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            once()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        fl = net.conv_flops(B, n, train)
+        tf = fl / (ms * 1e-3) / 1e12
+        out[key] = {"ms": round(ms, 3), "conv_gflop": round(fl / 1e9, 2), "tflops": round(tf, 2),
+                    "frac_bf16_dense_peak": round(tf / BF16_PEAK_TFLOPS, 5)}
+    log("cnn: %s" % out)
+    return out
+
+
 def measured_traffic():
     """HBM bytes per sweep launch from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel), or None
@@ -240,6 +280,7 @@ def main():
             torch.cuda.empty_cache()
 
     steady = None if args.headline_only else warm_vs_cold()
+    cnn = None if args.headline_only else cnn_throughput()
     cpu = None if args.no_cpu else cpu_baseline()
     achieved = head["achieved_gbs"]
     traffic = measured_traffic() if n == 512 else None
@@ -271,6 +312,7 @@ def main():
         "membench_gbs": mb,
         "variants": variants,
         "steady_state": steady,
+        "warm_start_network": cnn,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -29,6 +29,17 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD
+// b % 8).  Renumbering them so that each XCD works through one contiguous
+// range of tiles keeps the neighbouring tiles that share input voxels in the
+// same L2.  The grid is launched padded to a multiple of 8; indices at or
+// beyond n_real mark padding workgroups, which exit.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n_launched) {
+  const int64_t per = n_launched / kXcds;
+  return (b % kXcds) * per + b / kXcds;
+}
+
 struct Geom {
   int B, D, H, W;     // input grid
   int Do, Ho, Wo;     // output grid
@@ -50,103 +61,183 @@ __device__ __forceinline__ void tap_offsets(int tap, int taps, int& dz, int& dy,
 }
 
 // ---- forward --------------------------------------------------------------
-template <int STRIDE, int TAPS, int NB, bool OUTF32>
+// A wavefront owns MT consecutive 16-voxel tiles and all NB 16-channel
+// output blocks: per tap and 16-channel input chunk it loads MT A fragments
+// and NB B fragments and issues MT x NB MFMAs, so each weight fragment
+// serves MT tiles and each input fragment NB output blocks.  The periodic
+// neighbour of a lane's voxel is found from per-axis offsets computed once
+// (the taps are unrolled, so each tap just adds three of them).
+struct AxisOff {
+  int base;     // input voxel index of the tap (0, 0, 0) source
+  int oz[3], oy[3], ox[3];  // voxel-index offsets of the sources at -1, 0, +1
+};
+
+// Offsets of the sources s*c + d (d = -1, 0, 1; periodic) on one axis of
+// extent n, scaled by that axis' voxel stride.
+__device__ __forceinline__ void axis_offsets(int c, int s, int n, int stride, int (&o)[3]) {
+  const int c0 = s * c;
+#pragma unroll
+  for (int d = -1; d <= 1; ++d) o[d + 1] = (wrapi(c0 + d, n) - c0) * stride;
+}
+
+template <int STRIDE, int TAPS, int NB, bool OUTF32, int MT>
 __global__ void __launch_bounds__(256)
 k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
            const float* __restrict__ bias, void* __restrict__ y, Geom g) {
   const int lane = threadIdx.x & 63;
-  const int64_t v0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  const int64_t blk = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t v0 = (blk * 4 + (threadIdx.x >> 6)) * 16 * MT;
   if (v0 >= g.m_out) return;
   const int row = lane & 15, kq = lane >> 4;
-  // the output voxel of this lane's A row (tiles may span grid rows)
-  int64_t t = v0 + row;
-  const int xo = (int)(t % g.Wo);
-  t /= g.Wo;
-  const int yo = (int)(t % g.Ho);
-  t /= g.Ho;
-  const int zo = (int)(t % g.Do);
-  const int b = (int)(t / g.Do);
-  f4 acc[NB];
+  AxisOff ao[MT];
+  bool live[MT];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) acc[nb] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < MT; ++m) {
+    live[m] = v0 + 16 * m < g.m_out;
+    int64_t t = live[m] ? v0 + 16 * m + row : 0;
+    const int xo = (int)(t % g.Wo);
+    t /= g.Wo;
+    const int yo = (int)(t % g.Ho);
+    t /= g.Ho;
+    const int zo = (int)(t % g.Do);
+    const int b = (int)(t / g.Do);
+    ao[m].base = ((b * g.D + STRIDE * zo) * g.H + STRIDE * yo) * g.W + STRIDE * xo;
+    axis_offsets(zo, STRIDE, g.D, g.H * g.W, ao[m].oz);
+    axis_offsets(yo, STRIDE, g.H, g.W, ao[m].oy);
+    axis_offsets(xo, STRIDE, g.W, 1, ao[m].ox);
+  }
+  f4 acc[MT][NB];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f4{0.f, 0.f, 0.f, 0.f};
+  const uint16_t* xl = x + 4 * kq;
+#pragma unroll
   for (int tap = 0; tap < TAPS; ++tap) {
-    int dz, dy, dx;
-    tap_offsets(tap, TAPS, dz, dy, dx);
-    const int zi = wrapi(STRIDE * zo + dz, g.D);
-    const int yi = wrapi(STRIDE * yo + dy, g.H);
-    const int xi = wrapi(STRIDE * xo + dx, g.W);
-    const uint16_t* xp = x + ((((int64_t)b * g.D + zi) * g.H + yi) * g.W + xi) * g.ci + 4 * kq;
+    const int iz = TAPS == 27 ? tap / 9 : 1, iy = TAPS == 27 ? (tap / 3) % 3 : 1,
+              ix = TAPS == 27 ? tap % 3 : 1;
+    const uint16_t* xp[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+      xp[m] = xl + (int64_t)(ao[m].base + ao[m].oz[iz] + ao[m].oy[iy] + ao[m].ox[ix]) * g.ci;
     const uint16_t* wp = w + ((int64_t)tap * g.co + row) * g.ci + 4 * kq;
     for (int c0 = 0; c0 < g.ci; c0 += 16) {
-      const s4 a = *(const s4*)(xp + c0);
+      s4 a[MT], bv[NB];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const s4 bv = *(const s4*)(wp + (int64_t)nb * 16 * g.ci + c0);
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[nb], 0, 0, 0);
-      }
+      for (int m = 0; m < MT; ++m) a[m] = *(const s4*)(xp[m] + c0);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) bv[nb] = *(const s4*)(wp + (int64_t)nb * 16 * g.ci + c0);
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], bv[nb], acc[m][nb], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    const int co = nb * 16 + row;
-    if (co >= g.cstore) continue;
-    const float bb = bias ? bias[co] : 0.f;
+  for (int m = 0; m < MT; ++m) {
+    if (!live[m]) continue;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t vox = v0 + 4 * kq + r;
-      float v = acc[nb][r] + bb;
-      if (g.act) v = v > 0.f ? v : v * g.slope;
-      if (OUTF32) ((float*)y)[vox * g.cstore + co] = v;
-      else ((uint16_t*)y)[vox * g.cstore + co] = f2bf(v);
+    for (int nb = 0; nb < NB; ++nb) {
+      const int co = nb * 16 + row;
+      if (co >= g.cstore) continue;
+      const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t vox = v0 + 16 * m + 4 * kq + r;
+        float v = acc[m][nb][r] + bb;
+        if (g.act) v = v > 0.f ? v : v * g.slope;
+        if (OUTF32) ((float*)y)[vox * g.cstore + co] = v;
+        else ((uint16_t*)y)[vox * g.cstore + co] = f2bf(v);
+      }
     }
   }
 }
 
 // ---- data gradient --------------------------------------------------------
-// dx[q] = sum over taps and output voxels p with s*p + off = q of W^T dy[p].
-template <int STRIDE, int TAPS, int NB>
+// dx[q] = sum over taps and output voxels p with s*p + off = q of W^T dy[p];
+// MT input-voxel tiles per wavefront as in the forward kernel.  For tap
+// offset d on an axis the source is t = q - d (periodic); under stride 2
+// only even t are images of coarse voxels, at t / 2.
+template <int STRIDE, int TAPS, int NB, int MT>
 __global__ void __launch_bounds__(256)
 k_conv_dgrad(const uint16_t* __restrict__ dyp, const uint16_t* __restrict__ wt,
              float* __restrict__ dxp, int accumulate, Geom g) {
   const int lane = threadIdx.x & 63;
-  const int64_t q0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  const int64_t blk = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t q0 = (blk * 4 + (threadIdx.x >> 6)) * 16 * MT;
   if (q0 >= g.m_in) return;
   const int row = lane & 15, kq = lane >> 4;
-  int64_t t = q0 + row;
-  const int xq = (int)(t % g.W);
-  t /= g.W;
-  const int yq = (int)(t % g.H);
-  t /= g.H;
-  const int zq = (int)(t % g.D);
-  const int b = (int)(t / g.D);
-  f4 acc[NB];
+  // per tile: coarse-grid voxel offsets of the sources at d = -1, 0, +1 on
+  // each axis (index d + 1), and their validity (bit d + 1)
+  int base[MT], oz[MT][3], oy[MT][3], ox[MT][3];
+  uint32_t vz[MT], vy[MT], vx[MT];
+  bool live[MT];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) acc[nb] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < MT; ++m) {
+    live[m] = q0 + 16 * m < g.m_in;
+    int64_t t = live[m] ? q0 + 16 * m + row : 0;
+    const int xq = (int)(t % g.W);
+    t /= g.W;
+    const int yq = (int)(t % g.H);
+    t /= g.H;
+    const int zq = (int)(t % g.D);
+    const int b = (int)(t / g.D);
+    base[m] = b * g.Do * g.Ho * g.Wo;
+    vz[m] = vy[m] = vx[m] = 0;
+#pragma unroll
+    for (int d = -1; d <= 1; ++d) {
+      const int tz = wrapi(zq - d, g.D), ty = wrapi(yq - d, g.H), tx = wrapi(xq - d, g.W);
+      oz[m][d + 1] = (tz / STRIDE) * g.Ho * g.Wo;
+      oy[m][d + 1] = (ty / STRIDE) * g.Wo;
+      ox[m][d + 1] = tx / STRIDE;
+      if (STRIDE == 1 || (tz & 1) == 0) vz[m] |= 1u << (d + 1);
+      if (STRIDE == 1 || (ty & 1) == 0) vy[m] |= 1u << (d + 1);
+      if (STRIDE == 1 || (tx & 1) == 0) vx[m] |= 1u << (d + 1);
+    }
+  }
+  f4 acc[MT][NB];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f4{0.f, 0.f, 0.f, 0.f};
+  const uint16_t* dl = dyp + 4 * kq;
+#pragma unroll
   for (int tap = 0; tap < TAPS; ++tap) {
-    int dz, dy, dx;
-    tap_offsets(tap, TAPS, dz, dy, dx);
-    const int tz = wrapi(zq - dz, g.D), ty = wrapi(yq - dy, g.H), tx = wrapi(xq - dx, g.W);
-    // stride 2: only even fine coordinates are images of coarse voxels
-    const bool valid = STRIDE == 1 || ((tz | ty | tx) & 1) == 0;
-    const int pz = tz / STRIDE, py = ty / STRIDE, px = tx / STRIDE;
-    const uint16_t* ap = dyp + ((((int64_t)b * g.Do + pz) * g.Ho + py) * g.Wo + px) * g.co + 4 * kq;
+    const int iz = TAPS == 27 ? tap / 9 : 1, iy = TAPS == 27 ? (tap / 3) % 3 : 1,
+              ix = TAPS == 27 ? tap % 3 : 1;
+    const uint16_t* ap[MT];
+    bool valid[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      valid[m] = ((vz[m] >> iz) & (vy[m] >> iy) & (vx[m] >> ix) & 1u) != 0;
+      ap[m] = dl + (int64_t)(base[m] + oz[m][iz] + oy[m][iy] + ox[m][ix]) * g.co;
+    }
     const uint16_t* bp = wt + ((int64_t)tap * g.ci + row) * g.co + 4 * kq;
     for (int c0 = 0; c0 < g.co; c0 += 16) {
-      s4 a = valid ? *(const s4*)(ap + c0) : s4{0, 0, 0, 0};
+      s4 a[MT], bv[NB];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const s4 bv = *(const s4*)(bp + (int64_t)nb * 16 * g.co + c0);
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[nb], 0, 0, 0);
-      }
+      for (int m = 0; m < MT; ++m) a[m] = valid[m] ? *(const s4*)(ap[m] + c0) : s4{0, 0, 0, 0};
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) bv[nb] = *(const s4*)(bp + (int64_t)nb * 16 * g.co + c0);
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], bv[nb], acc[m][nb], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    const int c = nb * 16 + row;
+  for (int m = 0; m < MT; ++m) {
+    if (!live[m]) continue;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      float* o = dxp + (q0 + 4 * kq + r) * g.ci + c;
-      *o = accumulate ? *o + acc[nb][r] : acc[nb][r];
+    for (int nb = 0; nb < NB; ++nb) {
+      const int c = nb * 16 + row;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float* o = dxp + (q0 + 16 * m + 4 * kq + r) * g.ci + c;
+        *o = accumulate ? *o + acc[m][nb][r] : acc[m][nb][r];
+      }
     }
   }
 }
@@ -198,7 +289,9 @@ k_conv_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dyp,
   uint16_t* xT = wg_lds + g.co * kWgRow;    // [tpb][ci][kWgRow]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tap0 = blockIdx.y * tpb;
-  const int64_t start = (int64_t)blockIdx.x * chunk;
+  const int64_t ck = xcd_tile(blockIdx.x, gridDim.x);  // this block's chunk
+  const int64_t start = ck * chunk;
+  if (start >= g.m_out) return;  // padding workgroup (before any barrier)
   int64_t end = start + chunk;
   if (end > g.m_out) end = g.m_out;
   const int nbi = g.ci / 16, nt = (g.co / 16) * nbi, ntiles = tpb * nt;
@@ -283,7 +376,7 @@ k_conv_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dyp,
     if (tile < ntiles) {
       const int tl = tile / nt, t2 = tile - tl * nt;
       const int mo = t2 / nbi, ni = t2 - mo * nbi;
-      float* out = partial + ((int64_t)blockIdx.x * TAPS + tap0 + tl) * g.co * g.ci;
+      float* out = partial + (ck * TAPS + tap0 + tl) * g.co * g.ci;
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         out[(mo * 16 + 4 * kq + r) * g.ci + ni * 16 + row] = acc[j][r];
@@ -503,6 +596,7 @@ __global__ void k_to_bf16(const float* __restrict__ s, uint16_t* __restrict__ d,
 }
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+static inline unsigned pad_xcd(unsigned n) { return (n + kXcds - 1) / kXcds * kXcds; }
 
 static int check_desc(const nn_conv_desc* d) {
   if (!d) { set_error("descriptor is NULL"); return -1; }
@@ -516,6 +610,7 @@ static int check_desc(const nn_conv_desc* d) {
     return -1;
   }
   const int64_t m_in = (int64_t)d->batch * d->d * d->h * d->w;
+  if (m_in >= 0x7fffffffLL) { set_error("more than 2^31 voxels"); return -1; }
   if (m_in % (16 * d->stride * d->stride * d->stride)) {
     set_error("voxel counts of the input and output grids must be multiples of 16");
     return -1;
@@ -582,13 +677,42 @@ static int64_t wgrad_chunk(const nn_conv_desc* d, const Geom& g, int64_t* chunks
   return per;
 }
 
+// Tiles per wavefront: four while that still leaves about 4096 waves.
+static int pick_mt(int64_t m) { return m >= 4 * 16 * 4096 ? 4 : (m >= 2 * 16 * 4096 ? 2 : 1); }
+
+template <int STRIDE, int TAPS, bool F32, int MT>
+static void launch_fwd_mt(int nb, const uint16_t* x, const uint16_t* w, const float* bias, void* y,
+                          const Geom& g, hipStream_t s) {
+  const dim3 grid(pad_xcd(nblk(g.m_out / 16, 4 * MT))), block(256);
+  switch (nb) {
+#define CASE(N)                                                                                  \
+  case N:                                                                                        \
+    hipLaunchKernelGGL((k_conv_fwd<STRIDE, TAPS, N, F32, MT>), grid, block, 0, s, x, w, bias, y, g); \
+    break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+  }
+}
+
 template <int STRIDE, int TAPS, bool F32>
 static void launch_fwd_nb(int nb, const uint16_t* x, const uint16_t* w, const float* bias, void* y,
                           const Geom& g, hipStream_t s) {
-  const dim3 grid(nblk(g.m_out / 16, 4)), block(256);
+  switch (pick_mt(g.m_out)) {
+    case 4: launch_fwd_mt<STRIDE, TAPS, F32, 4>(nb, x, w, bias, y, g, s); break;
+    case 2: launch_fwd_mt<STRIDE, TAPS, F32, 2>(nb, x, w, bias, y, g, s); break;
+    default: launch_fwd_mt<STRIDE, TAPS, F32, 1>(nb, x, w, bias, y, g, s); break;
+  }
+}
+
+template <int STRIDE, int TAPS, int MT>
+static void launch_dgrad_mt(int nb, const uint16_t* dy, const uint16_t* wt, float* dx, int acc,
+                            const Geom& g, hipStream_t s) {
+  const dim3 grid(pad_xcd(nblk(g.m_in / 16, 4 * MT))), block(256);
   switch (nb) {
-#define CASE(N) \
-  case N: hipLaunchKernelGGL((k_conv_fwd<STRIDE, TAPS, N, F32>), grid, block, 0, s, x, w, bias, y, g); break;
+#define CASE(N)                                                                                   \
+  case N:                                                                                         \
+    hipLaunchKernelGGL((k_conv_dgrad<STRIDE, TAPS, N, MT>), grid, block, 0, s, dy, wt, dx, acc, g); \
+    break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
   }
@@ -597,12 +721,10 @@ static void launch_fwd_nb(int nb, const uint16_t* x, const uint16_t* w, const fl
 template <int STRIDE, int TAPS>
 static void launch_dgrad_nb(int nb, const uint16_t* dy, const uint16_t* wt, float* dx, int acc,
                             const Geom& g, hipStream_t s) {
-  const dim3 grid(nblk(g.m_in / 16, 4)), block(256);
-  switch (nb) {
-#define CASE(N) \
-  case N: hipLaunchKernelGGL((k_conv_dgrad<STRIDE, TAPS, N>), grid, block, 0, s, dy, wt, dx, acc, g); break;
-    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
-#undef CASE
+  switch (pick_mt(g.m_in)) {
+    case 4: launch_dgrad_mt<STRIDE, TAPS, 4>(nb, dy, wt, dx, acc, g, s); break;
+    case 2: launch_dgrad_mt<STRIDE, TAPS, 2>(nb, dy, wt, dx, acc, g, s); break;
+    default: launch_dgrad_mt<STRIDE, TAPS, 1>(nb, dy, wt, dx, acc, g, s); break;
   }
 }
 
@@ -610,7 +732,7 @@ template <int STRIDE, int TAPS>
 static void launch_wgrad_tpw(int tpw, int tpb, size_t lds, const uint16_t* x, const uint16_t* dy,
                              float* partial, int64_t chunk, int64_t chunks, const Geom& g,
                              hipStream_t s) {
-  const dim3 grid((unsigned)chunks, TAPS / tpb), block(256);
+  const dim3 grid(pad_xcd((unsigned)chunks), TAPS / tpb), block(256);
   const int t = tpw <= 2 ? 2 : (tpw <= 4 ? 4 : (tpw <= 8 ? 8 : 14));
   switch (t) {
 #define CASE(N)                                                                                   \

@@ -161,6 +161,22 @@ class UNet:
                 "e3a": 3, "e3": 3, "u2a": 2, "u2": 2, "u1a": 1, "u1": 1, "u0a": 0, "u0": 0,
                 "head": 0}[name]
 
+    def conv_flops(self, batch, n, train=False):
+        """Multiply-add flops (2 per MAC) of the convolutions for one forward
+        pass, or for a training step (forward, weight gradient and data
+        gradient of every layer except the first, which has no input
+        gradient).  Channel counts as the network defines them; the head
+        counts its 3 stored outputs."""
+        sizes = {0: n, 1: n // 2, 2: n // 4, 3: n // 8}
+        fwd = first = 0
+        for L in self.layers:
+            m_out = batch * (sizes[self._level_in(L.name)] // L.stride) ** 3
+            f = 2 * L.taps * L.c_in * L.c_store * m_out
+            fwd += f
+            if L.name == "e0a":
+                first = f
+        return 3 * fwd - first if train else fwd
+
     # -- forward ----------------------------------------------------------------
     def forward(self, mask_u8, batch, n):
         """mask_u8: device uint8 [batch*n^3]; returns the float32 output
