@@ -80,20 +80,12 @@ __device__ __forceinline__ uint32_t mix32(uint32_t h) {
   return h;
 }
 
-// float -> half with stochastic rounding: add 13 random bits below the last
-// half-precision mantissa bit of the magnitude, then truncate; the result is
-// exactly representable, so the conversion itself is exact.  Rounds up with
-// probability equal to the fraction of the ulp, so the expected stored value
-// equals the input (small increments are not lost).  Values outside the
-// normal half range fall back to round-to-nearest-even.
-__device__ __forceinline__ _Float16 f32_to_f16_stochastic(float v, uint32_t rnd) {
-  const uint32_t b = __float_as_uint(v);
-  uint32_t mag = b & 0x7fffffffu;
-  if (mag < 0x38800000u || mag >= 0x477fe000u) return (_Float16)v;
-  mag = (mag + (rnd & 0x1fffu)) & ~0x1fffu;
-  if (mag > 0x477fe000u) mag = 0x477fe000u;
-  return (_Float16)__uint_as_float((b & 0x80000000u) | mag);
-}
+// float -> half with stochastic rounding, by the gfx950 conversion
+// instruction: it adds the top 13 bits of the random word below the last
+// half-precision mantissa bit of the magnitude and truncates, so a value
+// rounds up with probability equal to its fraction of an ulp and the
+// expected stored value equals the input (small increments are not lost).
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
 struct StoreF16ShiftedSR {
   using T = _Float16;
@@ -101,24 +93,26 @@ struct StoreF16ShiftedSR {
   static constexpr bool kShifted = true;
   static constexpr bool kStochastic = true;
   __device__ __forceinline__ static R load(T v, R inv_scale) { return (R)v * inv_scale; }
-  // rnd: 13 uniformly distributed random bits in the low bits
+  // rnd: a random word whose top 13 bits are uniformly distributed
   __device__ __forceinline__ static T store(R v, R scale, uint32_t rnd) {
-    return f32_to_f16_stochastic(v * scale, rnd);
+    const half2_t z = {(_Float16)0, (_Float16)0};
+    return __builtin_amdgcn_cvt_sr_f16_f32(z, v * scale, rnd, false)[0];
   }
 };
 
 // Random bits for stochastic rounding.  One hash per (node, time step):
 // mix32 of the node index xor a hash of the step; the 19 values of the node
 // then take successive states of a 32-bit linear congruential generator
-// (Numerical Recipes constants) seeded with it, using its top 13 bits (the
-// well-mixed ones).  Deterministic: a function of (node, direction, step).
+// (Numerical Recipes constants) seeded with it; the conversion uses the top
+// 13 bits of each state (the well-mixed ones).  Deterministic: a function of
+// (node, direction, step).
 struct SrStream {
   uint32_t s;
   __device__ __forceinline__ SrStream(uint32_t node, uint32_t step, bool on)
       : s(on ? mix32(node * 0x9E3779B1u ^ mix32(step * 0x85ebca77u + 0x165667b1u)) : 0u) {}
   __device__ __forceinline__ uint32_t next() {
     s = s * 1664525u + 1013904223u;
-    return s >> 19;
+    return s;
   }
 };
 
