@@ -27,15 +27,15 @@ def L():
     return lbm
 
 
-def _oracle_u(ny, nz, nx, steps=None, tol=None):
+def _oracle_u(ny, nz, nx, steps=None, tol=None, bounce=0):
     """Oracle velocity [3][N] of the nx x ny x nz channel: after `steps`
     updates, or at steady state (residual < tol)."""
     m1 = I.channel_mask(1, ny, nz)
-    f = O.rest_state(m1, 0)
+    f = O.rest_state(m1, bounce)
     if steps is not None:
-        f = O.run(m1, f, steps, PHYS["tau_plus"], PHYS["magic"], PHYS["g"], 0)
+        f = O.run(m1, f, steps, PHYS["tau_plus"], PHYS["magic"], PHYS["g"], bounce)
     else:
-        f, _, _ = O.run_to_steady(m1, f, PHYS["tau_plus"], PHYS["magic"], PHYS["g"], 0, tol, 500)
+        f, _, _ = O.run_to_steady(m1, f, PHYS["tau_plus"], PHYS["magic"], PHYS["g"], bounce, tol, 500)
     u = O.macroscopic(m1, f, PHYS["g"])[1].reshape(nz, ny, 1, 3)
     u = np.broadcast_to(u, (nz, ny, nx, 3)).reshape(-1, 3)
     return np.ascontiguousarray(u.T)
@@ -107,3 +107,39 @@ def test_shifted_mass_conservation(L, storage):
     assert abs(s0["mass"] - mask.size) <= 1e-12 * mask.size
     rel = abs(s1["mass"] - s0["mass"]) / s0["mass"]
     assert rel <= (1e-9 if storage == "f32s" else 1e-5)
+
+
+FORMS = [
+    {"layout": "aos"}, {"bounce": "halfway"},
+    {"propagation": "aa"}, {"propagation": "aa", "layout": "aos"},
+    {"propagation": "push"}, {"propagation": "push", "layout": "aos"},
+    {"addressing": "list", "bounce": "halfway"},
+    {"addressing": "list", "bounce": "halfway", "layout": "aos"},
+    {"addressing": "list", "bounce": "halfway", "propagation": "aa"},
+    {"addressing": "list", "bounce": "halfway", "propagation": "push"},
+    {"addressing": "ria", "bounce": "halfway"},
+    {"addressing": "ria", "bounce": "halfway", "propagation": "aa"},
+    {"addressing": "ria", "bounce": "halfway", "propagation": "push"},
+]
+_REF = {}
+
+
+@pytest.mark.parametrize("storage,tol", [("f32s", 1e-5), ("f16sr", 1e-3)])
+@pytest.mark.parametrize("form", range(len(FORMS)))
+def test_equal_step_error_every_form(L, storage, tol, form):
+    """Shifted storage in every layout, addressing and propagation form:
+    600 updates of the 64x32x32 channel against the FP64 oracle with the
+    same bounce-back (the storage scale and rounding enter each kernel's
+    own load and store paths)."""
+    import torch
+    kw = FORMS[form]
+    bounce = 1 if kw.get("bounce") == "halfway" else 0
+    steps = 600
+    if bounce not in _REF:
+        _REF[bounce] = _oracle_u(32, 32, 64, steps=steps, bounce=bounce)
+    ref = _REF[bounce]
+    lat = L.Lattice(I.channel_mask(64, 32, 32), storage=storage, **PHYS, **kw)
+    lat.step(steps)
+    v = lat.verify(L.VERIFY_REFERENCE, torch.from_numpy(ref.reshape(-1)).to(lat.device))
+    print(storage, kw, v)
+    assert v["rel_l2"] <= tol
