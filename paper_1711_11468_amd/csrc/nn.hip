@@ -282,7 +282,8 @@ static_assert(kWgRow % 4 == 0, "8-byte aligned operand rows");
 template <int STRIDE, int TAPS, int TPW>
 __global__ void __launch_bounds__(256)
 k_conv_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dyp,
-             float* __restrict__ partial, int64_t chunk, int tpb, Geom g) {
+             float* __restrict__ partial, float* __restrict__ bias_partial, int64_t chunk, int tpb,
+             Geom g) {
   extern __shared__ __align__(16) uint16_t wg_lds[];
   __shared__ int vb[64][4];
   uint16_t* dyT = wg_lds;                   // [co][kWgRow]
@@ -297,6 +298,10 @@ k_conv_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dyp,
   const int nbi = g.ci / 16, nt = (g.co / 16) * nbi, ntiles = tpb * nt;
   const int cvo = g.co / 8, cvi = g.ci / 8;
   const int row = lane & 15, kq = lane >> 4;
+  // the bias gradient of this chunk (sum of dy over its voxels), by the
+  // first tap group's blocks, one thread per output channel
+  const bool do_bias = bias_partial != nullptr && blockIdx.y == 0 && tid < g.co;
+  float bsum = 0.f;
   f4 acc[TPW];
   int aoff[TPW], boff[TPW];  // LDS element offsets of this lane's operands, per tile
 #pragma unroll
@@ -358,6 +363,10 @@ k_conv_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dyp,
       store_t4(xT + (tl * g.ci + cv * 8) * kWgRow + 4 * p4, v);
     }
     __syncthreads();
+    if (do_bias) {
+      const uint16_t* r = dyT + tid * kWgRow;
+      for (int p = 0; p < 64; ++p) bsum += bf2f(r[p]);
+    }
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       if (wave + 4 * j < ntiles) {
@@ -370,6 +379,7 @@ k_conv_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dyp,
       }
     }
   }
+  if (do_bias) bias_partial[ck * g.co + tid] = bsum;
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     const int tile = wave + 4 * j;
@@ -407,29 +417,6 @@ __global__ void k_sum_chunks(const float* __restrict__ partial, float* __restric
   float s = 0.f;
   for (int64_t c = 0; c < chunks; ++c) s += partial[c * n + i];
   out[i] = s;
-}
-
-// Bias gradient partials: block per chunk, fixed-order combination.
-__global__ void __launch_bounds__(256)
-k_bias_partial(const uint16_t* __restrict__ dyp, float* __restrict__ partial, int64_t chunk,
-               int64_t m, int co) {
-  __shared__ float sm[256];
-  const int tid = threadIdx.x;
-  const int groups = 256 / co;
-  const int c = tid % co, gidx = tid / co;
-  const int64_t start = (int64_t)blockIdx.x * chunk;
-  int64_t end = start + chunk;
-  if (end > m) end = m;
-  float s = 0.f;
-  if (gidx < groups)
-    for (int64_t p = start + gidx; p < end; p += groups) s += bf2f(dyp[p * co + c]);
-  sm[tid] = s;
-  __syncthreads();
-  if (tid < co) {
-    float tot = 0.f;
-    for (int k = 0; k < groups; ++k) tot += sm[k * co + tid];
-    partial[(int64_t)blockIdx.x * co + tid] = tot;
-  }
 }
 
 // ---- elementwise ----------------------------------------------------------
@@ -529,16 +516,31 @@ k_mse_partial(const float* __restrict__ pred, const float* __restrict__ tgt,
   }
 }
 
-__global__ void k_mse_final(const float* __restrict__ partial, int nblocks, float* __restrict__ loss,
-                            float* __restrict__ count) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One block: strided per-thread sums, then a fixed-order tree in LDS.
+__global__ void __launch_bounds__(256)
+k_mse_final(const float* __restrict__ partial, int nblocks, float* __restrict__ loss,
+            float* __restrict__ count) {
+  __shared__ float se[256], sc[256];
+  const int t = threadIdx.x;
   float e = 0.f, c = 0.f;
-  for (int b = 0; b < nblocks; ++b) {
+  for (int b = t; b < nblocks; b += 256) {
     e += partial[2 * b];
     c += partial[2 * b + 1];
   }
-  *count = c;
-  *loss = c > 0.f ? e / (3.f * c) : 0.f;
+  se[t] = e;
+  sc[t] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      se[t] += se[t + w];
+      sc[t] += sc[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    *count = sc[0];
+    *loss = sc[0] > 0.f ? se[0] / (3.f * sc[0]) : 0.f;
+  }
 }
 
 __global__ void k_mse_grad(const float* __restrict__ pred, const float* __restrict__ tgt,
@@ -658,16 +660,16 @@ static void wgrad_plan(const nn_conv_desc* d, int* tpb, int* tpw, size_t* lds) {
 }
 
 // Voxel chunks of the weight gradient (a multiple of 64 voxels each): about
-// 2048 blocks over chunks and tap groups, with the per-chunk partials
-// (taps x co x ci floats each) kept under 64 MiB.
+// 1024 blocks over chunks and tap groups, with the per-chunk partials
+// (taps x co x ci floats each) kept under 32 MiB.
 static int64_t wgrad_chunk(const nn_conv_desc* d, const Geom& g, int64_t* chunks) {
   int tpb, tpw;
   size_t lds;
   wgrad_plan(d, &tpb, &tpw, &lds);
   const int groups = d->taps / tpb;
-  int64_t c = (2048 + groups - 1) / groups;
+  int64_t c = (1024 + groups - 1) / groups;
   const int64_t per_chunk_bytes = (int64_t)d->taps * d->c_out * d->c_in * 4;
-  const int64_t cap = (int64_t)64 * 1024 * 1024 / per_chunk_bytes;
+  const int64_t cap = (int64_t)32 * 1024 * 1024 / per_chunk_bytes;
   if (c > cap) c = cap;
   if (c > (g.m_out + 63) / 64) c = (g.m_out + 63) / 64;
   if (c < 1) c = 1;
@@ -730,15 +732,15 @@ static void launch_dgrad_nb(int nb, const uint16_t* dy, const uint16_t* wt, floa
 
 template <int STRIDE, int TAPS>
 static void launch_wgrad_tpw(int tpw, int tpb, size_t lds, const uint16_t* x, const uint16_t* dy,
-                             float* partial, int64_t chunk, int64_t chunks, const Geom& g,
-                             hipStream_t s) {
+                             float* partial, float* bias_partial, int64_t chunk, int64_t chunks,
+                             const Geom& g, hipStream_t s) {
   const dim3 grid(pad_xcd((unsigned)chunks), TAPS / tpb), block(256);
   const int t = tpw <= 2 ? 2 : (tpw <= 4 ? 4 : (tpw <= 8 ? 8 : 14));
   switch (t) {
 #define CASE(N)                                                                                   \
   case N:                                                                                         \
-    hipLaunchKernelGGL((k_conv_wgrad<STRIDE, TAPS, N>), grid, block, lds, s, x, dy, partial, chunk, \
-                       tpb, g);                                                                   \
+    hipLaunchKernelGGL((k_conv_wgrad<STRIDE, TAPS, N>), grid, block, lds, s, x, dy, partial,       \
+                       bias_partial, chunk, tpb, g);                                              \
     break;
     CASE(2) CASE(4) CASE(8) CASE(14)
 #undef CASE
@@ -819,25 +821,24 @@ int nn_conv3d_wgrad(const nn_conv_desc* d, const uint16_t* x, const uint16_t* dy
   hipStream_t s = (hipStream_t)stream;
   int64_t chunks;
   const int64_t chunk = wgrad_chunk(d, g, &chunks);
-  int tpb, tpw;
-  size_t lds;
-  wgrad_plan(d, &tpb, &tpw, &lds);
-  if (d->taps == 1) launch_wgrad_tpw<1, 1>(tpw, tpb, lds, x, dy, workspace, chunk, chunks, g, s);
-  else if (d->stride == 1) launch_wgrad_tpw<1, 27>(tpw, tpb, lds, x, dy, workspace, chunk, chunks, g, s);
-  else launch_wgrad_tpw<2, 27>(tpw, tpb, lds, x, dy, workspace, chunk, chunks, g, s);
   const int64_t nw = (int64_t)d->taps * d->c_out * d->c_in;
   const int64_t segs = (chunks + kSegLen - 1) / kSegLen;
   // workspace: [chunks][nw] partials, [segs][nw] segment sums, then the
   // same two areas for the bias (co each)
   float* wseg = workspace + chunks * nw;
+  float* bpart = wseg + segs * nw;
+  float* bseg = bpart + chunks * d->c_out;
+  int tpb, tpw;
+  size_t lds;
+  wgrad_plan(d, &tpb, &tpw, &lds);
+  float* bp = db ? bpart : nullptr;
+  if (d->taps == 1) launch_wgrad_tpw<1, 1>(tpw, tpb, lds, x, dy, workspace, bp, chunk, chunks, g, s);
+  else if (d->stride == 1) launch_wgrad_tpw<1, 27>(tpw, tpb, lds, x, dy, workspace, bp, chunk, chunks, g, s);
+  else launch_wgrad_tpw<2, 27>(tpw, tpb, lds, x, dy, workspace, bp, chunk, chunks, g, s);
   hipLaunchKernelGGL(k_sum_segments, dim3(nblk(nw, 256), (unsigned)segs), dim3(256), 0, s, workspace,
                      wseg, nw, chunks);
   hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(nw, 256)), dim3(256), 0, s, wseg, dw, nw, segs);
   if (db) {
-    float* bpart = wseg + segs * nw;
-    float* bseg = bpart + chunks * d->c_out;
-    hipLaunchKernelGGL(k_bias_partial, dim3((unsigned)chunks), dim3(256), 0, s, dy, bpart, chunk,
-                       g.m_out, d->c_out);
     hipLaunchKernelGGL(k_sum_segments, dim3(1, (unsigned)segs), dim3(256), 0, s, bpart, bseg,
                        (int64_t)d->c_out, chunks);
     hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, s, bseg, db, (int64_t)d->c_out, segs);
@@ -896,7 +897,7 @@ int nn_masked_mse(const float* pred, const float* target, const uint8_t* mask, i
   if (nb > 2046) nb = 2046;
   hipLaunchKernelGGL(k_mse_partial, dim3(nb), dim3(256), 0, s, pred, target, mask, n, workspace);
   float* count = workspace + 2 * 2046 + 1;
-  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, s, workspace, nb, loss, count);
+  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(256), 0, s, workspace, nb, loss, count);
   hipLaunchKernelGGL(k_mse_grad, dim3(nblk(n * 16, 256)), dim3(256), 0, s, pred, target, mask, n,
                      count, dy);
   NN_HIP_CHECK("masked mse");
