@@ -139,7 +139,7 @@ def warm_vs_cold(n=128, seeds=(100000, 100001, 100002)):
             "prediction_rel_l2_median": float(np.median([r["prediction_rel_l2"] for r in rows]))}
 
 
-def cnn_throughput(steps=10):
+def cnn_throughput(steps=10, which=("infer_128", "train_64x4")):
     """The warm-start network's BF16 MFMA convolutions: inference on one
     128^3 box and a training step on four 64^3 boxes (random weights and
     inputs; the work does not depend on the values), timed with HIP events
@@ -151,6 +151,8 @@ def cnn_throughput(steps=10):
     g = torch.Generator().manual_seed(0)
     out = {}
     for key, (B, n, train) in (("infer_128", (1, 128, False)), ("train_64x4", (4, 64, True))):
+        if key not in which:
+            continue
         mask = (torch.rand(B * n ** 3, generator=g) < 0.4).to(torch.uint8).to(dev)
         tgt = torch.randn(B * n ** 3 * 3, generator=g).to(dev)
 
@@ -226,9 +228,11 @@ def main():
     ap.add_argument("--n", type=int, default=512, help="channel edge (headline: 512)")
     ap.add_argument("--headline-only", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cnn-only", choices=["infer_128", "train_64x4", "both"], default=None,
+                    help="time only the warm-start network (for kernel traces)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only; this build runs no multi-GPU path "
+        print("bench.py measures one GPU only; the multi-GPU path is not implemented "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
@@ -238,6 +242,10 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     lbm.load()
+    if args.cnn_only:
+        which = ("infer_128", "train_64x4") if args.cnn_only == "both" else (args.cnn_only,)
+        print(json.dumps({"warm_start_network": cnn_throughput(which=which)}), flush=True)
+        return
     n = args.n
     mask = I.channel_mask(n, n, n)
     log("headline: channel %d^3 SoA fp64" % n)
