@@ -83,10 +83,14 @@ __device__ __forceinline__ void axis_offsets(int c, int s, int n, int stride, in
 template <int STRIDE, int TAPS, int NB, bool OUTF32, int MT>
 __global__ void __launch_bounds__(256)
 k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
-           const float* __restrict__ bias, void* __restrict__ y, Geom g) {
+           const float* __restrict__ bias, void* __restrict__ y, int nsplit, Geom g) {
   const int lane = threadIdx.x & 63;
   const int64_t blk = xcd_tile(blockIdx.x, gridDim.x);
-  const int64_t v0 = (blk * 4 + (threadIdx.x >> 6)) * 16 * MT;
+  // small grids: nsplit wavefronts share a tile, each with NB of the output
+  // channel blocks
+  const int64_t wv = blk * 4 + (threadIdx.x >> 6);
+  const int part = (int)(wv % nsplit);
+  const int64_t v0 = (wv / nsplit) * 16 * MT;
   if (v0 >= g.m_out) return;
   const int row = lane & 15, kq = lane >> 4;
   AxisOff ao[MT];
@@ -120,7 +124,7 @@ k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
 #pragma unroll
     for (int m = 0; m < MT; ++m)
       xp[m] = xl + (int64_t)(ao[m].base + ao[m].oz[iz] + ao[m].oy[iy] + ao[m].ox[ix]) * g.ci;
-    const uint16_t* wp = w + ((int64_t)tap * g.co + row) * g.ci + 4 * kq;
+    const uint16_t* wp = w + ((int64_t)tap * g.co + part * NB * 16 + row) * g.ci + 4 * kq;
     for (int c0 = 0; c0 < g.ci; c0 += 16) {
       s4 a[MT], bv[NB];
 #pragma unroll
@@ -139,7 +143,7 @@ k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
     if (!live[m]) continue;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const int co = nb * 16 + row;
+      const int co = (part * NB + nb) * 16 + row;
       if (co >= g.cstore) continue;
       const float bb = bias ? bias[co] : 0.f;
 #pragma unroll
@@ -450,6 +454,33 @@ __global__ void k_up_concat(const uint16_t* __restrict__ coarse, const uint16_t*
   }
 }
 
+// The same with 8 channels (16 bytes) per thread, for channel counts that
+// are multiples of 8.
+__global__ void k_up_concat8(const uint16_t* __restrict__ coarse, const uint16_t* __restrict__ skip,
+                             uint16_t* __restrict__ cat, int64_t nvox, int d, int h, int w, int c1,
+                             int c2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int g1 = c1 / 8, gt = (c1 + c2) / 8;
+  if (e >= nvox * gt) return;
+  const int64_t v = e / gt;
+  const int gi = (int)(e - v * gt);
+  uint4 val;
+  if (gi < g1) {
+    int64_t t = v;
+    const int xx = (int)(t % w);
+    t /= w;
+    const int yy = (int)(t % h);
+    t /= h;
+    const int zz = (int)(t % d);
+    const int b = (int)(t / d);
+    const int64_t cv = (((int64_t)b * (d / 2) + zz / 2) * (h / 2) + yy / 2) * (w / 2) + xx / 2;
+    val = *(const uint4*)(coarse + cv * c1 + gi * 8);
+  } else {
+    val = *(const uint4*)(skip + v * c2 + (gi - g1) * 8);
+  }
+  *(uint4*)(cat + v * (c1 + c2) + gi * 8) = val;
+}
+
 __global__ void k_split_down_coarse(const float* __restrict__ dcat, float* __restrict__ dcoarse,
                                     int64_t ncoarse, int d, int h, int w, int c1, int c2) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -685,11 +716,18 @@ static int pick_mt(int64_t m) { return m >= 4 * 16 * 4096 ? 4 : (m >= 2 * 16 * 4
 template <int STRIDE, int TAPS, bool F32, int MT>
 static void launch_fwd_mt(int nb, const uint16_t* x, const uint16_t* w, const float* bias, void* y,
                           const Geom& g, hipStream_t s) {
-  const dim3 grid(pad_xcd(nblk(g.m_out / 16, 4 * MT))), block(256);
-  switch (nb) {
+  // grids with fewer than 4096 wavefronts split the output channels
+  int nsplit = 1;
+  while (nsplit < nb && nb % (2 * nsplit) == 0 && (int64_t)nblk(g.m_out / 16, MT) * nsplit < 4096)
+    nsplit *= 2;
+  const int nbw = nb / nsplit;
+  const int64_t tiles = nblk(g.m_out / 16, MT);
+  const dim3 grid(pad_xcd(nblk(tiles * nsplit, 4))), block(256);
+  switch (nbw) {
 #define CASE(N)                                                                                  \
   case N:                                                                                        \
-    hipLaunchKernelGGL((k_conv_fwd<STRIDE, TAPS, N, F32, MT>), grid, block, 0, s, x, w, bias, y, g); \
+    hipLaunchKernelGGL((k_conv_fwd<STRIDE, TAPS, N, F32, MT>), grid, block, 0, s, x, w, bias, y,  \
+                       nsplit, g);                                                               \
     break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
@@ -864,8 +902,12 @@ int nn_up_concat(const uint16_t* coarse, const uint16_t* skip, uint16_t* cat, in
     return -1;
   }
   const int64_t nvox = (int64_t)batch * d * h * w;
-  hipLaunchKernelGGL(k_up_concat, dim3(nblk(nvox * (c1 + c2), 256)), dim3(256), 0,
-                     (hipStream_t)stream, coarse, skip, cat, nvox, d, h, w, c1, c2);
+  if (c1 % 8 == 0 && c2 % 8 == 0)
+    hipLaunchKernelGGL(k_up_concat8, dim3(nblk(nvox * ((c1 + c2) / 8), 256)), dim3(256), 0,
+                       (hipStream_t)stream, coarse, skip, cat, nvox, d, h, w, c1, c2);
+  else
+    hipLaunchKernelGGL(k_up_concat, dim3(nblk(nvox * (c1 + c2), 256)), dim3(256), 0,
+                       (hipStream_t)stream, coarse, skip, cat, nvox, d, h, w, c1, c2);
   NN_HIP_CHECK("up concat");
   return 0;
 }
