@@ -44,11 +44,15 @@
  *    equilibrium, TRT rates 1/tau+ and 1/tau- with
  *    tau- = 1/2 + Lambda/(tau+ - 1/2), split forcing with the
  *    (1 - 1/(2 tau)) prefactor on each half.
- *  - State alignment: the buffers hold post-collision populations of the
- *    pull scheme.  The canonical "pre-collision" state that export/import
- *    use is that buffer after one streaming (gather) pass, which is what a
- *    collide-then-stream implementation holds after the same number of
- *    updates.
+ *  - State alignment: for the one-step pull the buffers hold
+ *    post-collision populations.  The canonical "pre-collision" state that
+ *    export/import use is that buffer after one streaming (gather) pass,
+ *    which is what a collide-then-stream implementation holds after the
+ *    same number of updates.  The push buffers hold the canonical state
+ *    directly; the AA lattice holds it in place after an even number of
+ *    updates and as reversed post-collision values after an odd number.
+ *    Export and import translate every form, so the canonical state does
+ *    not depend on layout, addressing or propagation.
  */
 #ifndef LBM_MI355X_H
 #define LBM_MI355X_H
@@ -225,7 +229,10 @@ int lbm_init_fields(lbm_ctx* ctx, const double* rho_dev, const double* u_dev);
 
 /* Enqueue n fused stream-collide updates, one kernel launch each.
  * LBM_OS: source and destination buffers swap after every launch (Sect. 3
- * "One Step Kernels").  LBM_AA: one buffer; launches alternate between the
+ * "One Step Kernels"); each node gathers from its neighbours.  LBM_OS_PUSH:
+ * the same buffers, each node scatters its collided populations to its
+ * neighbours.  LIST_RIA runs the list kernels with run tables in place of
+ * the adjacency.  LBM_AA: one buffer; launches alternate between the
  * node-local kernel (read a node's populations, collide, write them back
  * reversed) and the neighbour kernel (read each population from the slot
  * the previous local step left it in at the neighbour, collide, write it
