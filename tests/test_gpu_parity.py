@@ -139,14 +139,16 @@ def test_block_size_bitwise_and_layouts_agree(L):
         assert rel_maxabs(run(**kw), ref) <= 1e-15, kw
 
 
-def test_full_size_channel_512_sampled(L):
-    """512^3 channel in the benchmark's launch configuration: sampled nodes
-    (corners, walls, interior) against the windowed oracle after 12 steps,
-    and every x-slice identical (x-invariance of the duct flow)."""
+@pytest.mark.parametrize("layout", ["soa", "aos"])
+def test_full_size_channel_512_sampled(L, layout):
+    """512^3 channel in the benchmark's launch configuration (both layouts
+    the benchmark times): sampled nodes (corners, walls, interior) against
+    the windowed oracle after 12 steps, and every x-slice identical
+    (x-invariance of the duct flow)."""
     n, steps = 512, 12
     mask = I.channel_mask(n, n, n)
     phys = dict(tau_plus=0.8, magic=3 / 16, g=(1e-6, 0.0, 0.0))
-    lat = L.Lattice(mask, **phys)
+    lat = L.Lattice(mask, layout=layout, **phys)
     lat.step(steps)
     pts = [(0, 1, 1), (5, 1, 2), (511, 2, 1), (100, 255, 256), (7, 510, 510), (300, 1, 300),
            (0, 0, 0), (400, 511, 17)]
