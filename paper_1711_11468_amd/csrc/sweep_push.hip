@@ -9,7 +9,7 @@ namespace lbm {
 // write f*_i to slot i of x + c_i in B (Sect. 3 "One Step Kernels").  B then
 // holds the pre-collision state of the next step in place.  The scattered,
 // misaligned row stores go through L2 as plain stores (the streaming
-// nontemporal form measured about 6 % slower here).  Full-way solid
+// nontemporal form measured about 6 % slower on MI355X).  Full-way solid
 // nodes send their reversed populations on; under half-way bounce-back a
 // population aimed at a solid node lands in slot opp(i) of the node itself.
 template <class ST, int LAYOUT, int BB>
