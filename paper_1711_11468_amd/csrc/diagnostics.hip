@@ -12,11 +12,10 @@ namespace lbm {
 View view_of(const lbm_ctx* c);
 
 constexpr int kReduceBlock = 256;
-constexpr int kMaxReduceGrid = 4096;
 
 static unsigned reduce_grid(int64_t n) {
   int64_t g = (n + kReduceBlock - 1) / kReduceBlock;
-  if (g > kMaxReduceGrid) g = kMaxReduceGrid;
+  if (g > kMaxReduceRecords) g = kMaxReduceRecords;
   return (unsigned)(g < 1 ? 1 : g);
 }
 
@@ -179,13 +178,17 @@ hipError_t launch_verify(lbm_ctx* c, const void* src, int kind, const double* re
 }
 
 // ---- final fixed-order reduction -----------------------------------------
+// Workgroup b combines records [b*chunk, min(n, (b+1)*chunk)) into record b
+// of `out`: strided per-thread sums, then the block reduction.
 __global__ void __launch_bounds__(kReduceBlock)
-k_final_reduce(const double* __restrict__ partials, int64_t n_blocks, int n_slots,
-               uint32_t max_mask, double* __restrict__ out) {
+k_reduce_records(const double* __restrict__ partials, int64_t n, int64_t chunk, int n_slots,
+                 uint32_t max_mask, double* __restrict__ out) {
   double acc[kStatSlots];
 #pragma unroll
   for (int s = 0; s < kStatSlots; ++s) acc[s] = 0.0;
-  for (int64_t b = threadIdx.x; b < n_blocks; b += blockDim.x) {
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  for (int64_t b = lo + threadIdx.x; b < hi; b += blockDim.x) {
 #pragma unroll
     for (int s = 0; s < kStatSlots; ++s) {
       if (s >= n_slots) break;
@@ -195,15 +198,27 @@ k_final_reduce(const double* __restrict__ partials, int64_t n_blocks, int n_slot
   }
   block_reduce<kStatSlots>(acc, max_mask);
   if (threadIdx.x == 0) {
-    for (int s = 0; s < n_slots; ++s) out[s] = acc[s];
+    for (int s = 0; s < n_slots; ++s) out[(int64_t)blockIdx.x * kStatSlots + s] = acc[s];
   }
 }
 
 hipError_t launch_final_reduce(lbm_ctx* c, double* partials, int64_t n_blocks, int n_slots,
                                uint32_t max_mask, double* out_dev) {
-  hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(kReduceBlock), 0, c->stream, partials,
-                     n_blocks, n_slots, max_mask, out_dev);
+  hipLaunchKernelGGL(k_reduce_records, dim3(1), dim3(kReduceBlock), 0, c->stream, partials,
+                     n_blocks, n_blocks, n_slots, max_mask, out_dev);
   return hipGetLastError();
+}
+
+hipError_t launch_reduce_records(lbm_ctx* c, double* partials, int64_t n, int n_slots,
+                                 uint32_t max_mask, double* stage, double* out_dev) {
+  if (n <= kMaxReduceRecords) return launch_final_reduce(c, partials, n, n_slots, max_mask, out_dev);
+  const int64_t chunk = (n + kMaxReduceRecords - 1) / kMaxReduceRecords;
+  const int64_t groups = (n + chunk - 1) / chunk;  // <= kMaxReduceRecords
+  hipLaunchKernelGGL(k_reduce_records, dim3((unsigned)groups), dim3(kReduceBlock), 0, c->stream,
+                     partials, n, chunk, n_slots, max_mask, stage);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_final_reduce(c, stage, groups, n_slots, max_mask, out_dev);
 }
 
 }  // namespace lbm

@@ -51,6 +51,11 @@ hipError_t launch_push(lbm_ctx* c, const void* src, void* dst);
 hipError_t launch_aa(lbm_ctx* c, void* buf);
 // Fluid list in AoS records: pull, push and both AA steps.
 hipError_t launch_list_aos(lbm_ctx* c, const void* src, void* dst);
+// The one-step pull (SoA direct) with the diagnostics of the state it reads
+// fused in: per-row partials (kStatSlots doubles each) into `partials`;
+// *rows = number of records written.
+hipError_t launch_pull_diag(lbm_ctx* c, const void* src, void* dst, int residual_mode,
+                            double* partials, int64_t* rows);
 // Run-length list (LIST_RIA): the pull and push sweeps and the AA
 // neighbour kernel (the AA local kernel needs no addressing).
 hipError_t launch_pull_ria(lbm_ctx* c, const void* src, void* dst);
@@ -73,6 +78,21 @@ hipError_t launch_verify(lbm_ctx* c, const void* src, int kind, const double* re
                          double* partials, int64_t* n_blocks_out);
 hipError_t launch_final_reduce(lbm_ctx* c, double* partials, int64_t n_blocks, int n_slots,
                                uint32_t max_mask, double* out_dev);
+// Fixed-order reduction of any number of partial records: contiguous groups
+// into at most kMaxReduceRecords records in `stage`, then one workgroup.
+hipError_t launch_reduce_records(lbm_ctx* c, double* partials, int64_t n, int n_slots,
+                                 uint32_t max_mask, double* stage, double* out_dev);
+constexpr int64_t kMaxReduceRecords = 4096;
+// Forms whose sweep can carry the diagnostics (one record per (y, z) row).
+inline bool fused_diag_form(const lbm_params& p) {
+  return p.propagation == LBM_OS && p.layout == LBM_SOA && p.addressing == LBM_DIRECT;
+}
+// Scratch layout: [records][kStatSlots] partials, [kMaxReduceRecords]
+// [kStatSlots] second-stage partials, [kStatSlots] result.
+inline int64_t stat_records(const lbm_params& p) {
+  const int64_t rows = fused_diag_form(p) ? (int64_t)p.ny * p.nz : 0;
+  return rows > kMaxReduceRecords ? rows : kMaxReduceRecords;
+}
 // Slot layouts of the two reductions.
 enum { M_MASS = 0, M_PX, M_PY, M_PZ, M_DU2, M_U2, M_UMAX, M_NONFINITE, M_COUNT };
 enum { V_MAXABS = 0, V_ERR2, V_REF2, V_REFMAX, V_COUNT_N, V_COUNT };

@@ -179,7 +179,7 @@ static int plan_sizes(const lbm_params* p, int64_t n_fluid, int64_t n_runs, lbm_
   const bool links = p->addressing == LBM_DIRECT && p->bounce == LBM_HALFWAY;
   if (links) s->links_bytes = round_up(N * 4, 256);
   s->u_prev_bytes = round_up(3 * (s->n_sites < 1 ? 1 : s->n_sites) * 8, 256);
-  s->scratch_bytes = round_up((int64_t)(4096 + 1) * kStatSlots * 8, 256);
+  s->scratch_bytes = round_up((stat_records(*p) + kMaxReduceRecords + 1) * kStatSlots * 8, 256);
   // Algorithmic HBM bytes per site update: 19 loads + 19 stores of one
   // element, plus the flag byte (direct, full-way), the link word (direct,
   // half-way), 18 int32 adjacency entries (list) or, for the run-length
@@ -452,6 +452,38 @@ int lbm_step(lbm_ctx* c, int32_t n) {
   return LBM_OK;
 }
 
+static double* stats_stage(const lbm_ctx* c) {
+  return (double*)c->b.scratch + stat_records(c->p) * kStatSlots;
+}
+
+static double* stats_result(const lbm_ctx* c) {
+  return stats_stage(c) + kMaxReduceRecords * kStatSlots;
+}
+
+// Downloads the reduced moments, fills *out and advances the residual
+// history; `step` is the update count of the state they describe.
+static int finish_stats(lbm_ctx* c, int residual_mode, int64_t step, lbm_stats* out) {
+  double r[kStatSlots];
+  LBM_HIP(hipMemcpyAsync(r, stats_result(c), sizeof(double) * M_COUNT, hipMemcpyDeviceToHost,
+                         c->stream),
+          "stats download");
+  LBM_HIP(hipStreamSynchronize(c->stream), "stats sync");
+  out->mass = r[M_MASS];
+  out->momentum[0] = r[M_PX];
+  out->momentum[1] = r[M_PY];
+  out->momentum[2] = r[M_PZ];
+  out->u_max = r[M_UMAX];
+  out->nonfinite = (int64_t)r[M_NONFINITE];
+  out->residual = residual_mode == 2 ? (r[M_U2] > 0 ? sqrt(r[M_DU2] / r[M_U2]) : (r[M_DU2] > 0 ? INFINITY : 0.0)) : -1.0;
+  out->step = step;
+  if (residual_mode > 0) c->u_prev_valid = 1;
+  if (out->nonfinite > 0) {
+    set_error("%lld fluid nodes hold non-finite populations", (long long)out->nonfinite);
+    return LBM_ENONFINITE;
+  }
+  return LBM_OK;
+}
+
 int lbm_macroscopic(lbm_ctx* c, double* rho_dev, double* u_dev, lbm_stats* out) {
   if (!c || !out) { set_error("ctx and out must be non-NULL"); return LBM_EINVAL; }
   LBM_HIP(hipSetDevice(c->device), "hipSetDevice");
@@ -463,26 +495,33 @@ int lbm_macroscopic(lbm_ctx* c, double* rho_dev, double* u_dev, lbm_stats* out) 
   int64_t nb = 0;
   LBM_HIP(launch_moments(c, pdf_buf(c, c->cur), rho_dev, u_dev, residual_mode, partials, &nb),
           "moments kernel");
-  double* res_dev = partials + 4096 * kStatSlots;
-  LBM_HIP(launch_final_reduce(c, partials, nb, M_COUNT, 1u << M_UMAX, res_dev), "reduce kernel");
-  double r[kStatSlots];
-  LBM_HIP(hipMemcpyAsync(r, res_dev, sizeof(double) * M_COUNT, hipMemcpyDeviceToHost, c->stream),
-          "stats download");
-  LBM_HIP(hipStreamSynchronize(c->stream), "stats sync");
-  out->mass = r[M_MASS];
-  out->momentum[0] = r[M_PX];
-  out->momentum[1] = r[M_PY];
-  out->momentum[2] = r[M_PZ];
-  out->u_max = r[M_UMAX];
-  out->nonfinite = (int64_t)r[M_NONFINITE];
-  out->residual = residual_mode == 2 ? (r[M_U2] > 0 ? sqrt(r[M_DU2] / r[M_U2]) : (r[M_DU2] > 0 ? INFINITY : 0.0)) : -1.0;
-  out->step = c->step;
-  if (residual_mode > 0) c->u_prev_valid = 1;
-  if (out->nonfinite > 0) {
-    set_error("%lld fluid nodes hold non-finite populations", (long long)out->nonfinite);
-    return LBM_ENONFINITE;
+  LBM_HIP(launch_final_reduce(c, partials, nb, M_COUNT, 1u << M_UMAX, stats_result(c)),
+          "reduce kernel");
+  return finish_stats(c, residual_mode, c->step, out);
+}
+
+int lbm_step_diag(lbm_ctx* c, lbm_stats* out) {
+  if (!c || !out) { set_error("ctx and out must be non-NULL"); return LBM_EINVAL; }
+  if (!fused_diag_form(c->p)) {
+    const int rc = lbm_macroscopic(c, nullptr, nullptr, out);
+    if (rc != LBM_OK && rc != LBM_ENONFINITE) return rc;
+    const int rs = lbm_step(c, 1);
+    return rs != LBM_OK ? rs : rc;
   }
-  return LBM_OK;
+  LBM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  const int residual_mode = c->b.u_prev ? (c->u_prev_valid ? 2 : 1) : 0;
+  double* partials = (double*)c->b.scratch;
+  int64_t rows = 0;
+  LBM_HIP(launch_pull_diag(c, pdf_buf(c, c->cur), pdf_buf(c, 1 - c->cur), residual_mode, partials,
+                           &rows),
+          "fused sweep launch");
+  const int64_t described = c->step;
+  c->cur = 1 - c->cur;
+  c->step += 1;
+  LBM_HIP(launch_reduce_records(c, partials, rows, M_COUNT, 1u << M_UMAX, stats_stage(c),
+                                stats_result(c)),
+          "reduce kernels");
+  return finish_stats(c, residual_mode, described, out);
 }
 
 int lbm_verify(lbm_ctx* c, int32_t kind, const double* ref_dev, lbm_verify_result* out) {
@@ -498,7 +537,7 @@ int lbm_verify(lbm_ctx* c, int32_t kind, const double* ref_dev, lbm_verify_resul
   double* partials = (double*)c->b.scratch;
   int64_t nb = 0;
   LBM_HIP(launch_verify(c, pdf_buf(c, c->cur), kind, ref_dev, partials, &nb), "verify kernel");
-  double* res_dev = partials + 4096 * kStatSlots;
+  double* res_dev = stats_result(c);
   LBM_HIP(launch_final_reduce(c, partials, nb, V_COUNT, (1u << V_MAXABS) | (1u << V_REFMAX), res_dev),
           "reduce kernel");
   double r[kStatSlots];

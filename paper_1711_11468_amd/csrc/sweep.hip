@@ -17,9 +17,50 @@
 // fluid node; 18 int32 adjacency entries give the slot to pull for each
 // moving direction, with periodicity and half-way bounce-back already
 // folded in, so the kernel has no geometry branches.
+#include "gather.hpp"
 #include "launch.hpp"
 
 namespace lbm {
+
+// Diagnostics fused into a sweep (the state it reads is the canonical state
+// before the update): per node the FP64 moments of the gathered populations,
+// accumulated as mass and momentum over every state-holding node and, over
+// fluid nodes, max |u|, the non-finite count and the residual sums against
+// (and then into) the velocity history u_prev [3][N].
+struct DiagArgs {
+  double gx, gy, gz;
+  double* u_prev;
+  int residual_mode;  // 0: none, 1: store u only, 2: sums against u_prev, then store
+  double* partials;   // [rows][kStatSlots]
+};
+
+template <class ST>
+__device__ __forceinline__ void diag_node(const typename ST::R (&f)[Q], bool fluid, int64_t n,
+                                          int64_t N, const DiagArgs& d, double (&acc)[M_COUNT]) {
+  double fd[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) fd[i] = ST::kShifted ? (double)f[i] + weight(i) : (double)f[i];
+  double rho, ux, uy, uz, jx, jy, jz;
+  moments_f64(fd, d.gx, d.gy, d.gz, rho, ux, uy, uz, jx, jy, jz);
+  acc[M_MASS] += rho;
+  acc[M_PX] += jx;
+  acc[M_PY] += jy;
+  acc[M_PZ] += jz;
+  if (!fluid) return;
+  if (!(isfinite(rho) && isfinite(jx) && isfinite(jy) && isfinite(jz))) acc[M_NONFINITE] += 1.0;
+  const double u2 = ux * ux + uy * uy + uz * uz;
+  acc[M_UMAX] = fmax(acc[M_UMAX], sqrt(u2));
+  if (d.residual_mode > 0) {
+    if (d.residual_mode == 2) {
+      const double ex = ux - d.u_prev[n], ey = uy - d.u_prev[N + n], ez = uz - d.u_prev[2 * N + n];
+      acc[M_DU2] += ex * ex + ey * ey + ez * ez;
+      acc[M_U2] += u2;
+    }
+    d.u_prev[n] = ux;
+    d.u_prev[N + n] = uy;
+    d.u_prev[2 * N + n] = uz;
+  }
+}
 
 template <class ST, int BB>
 __global__ void __launch_bounds__(1024)
@@ -70,6 +111,68 @@ k_sweep_soa(const typename ST::T* __restrict__ src, typename ST::T* __restrict__
   }
 }
 
+// The same sweep with the diagnostics of the state it reads: one partial
+// record per row (fixed-order block reduction), combined afterwards.  It
+// repeats the sweep's body rather than sharing it, so that the plain sweep's
+// code is untouched by the diagnostics.
+template <class ST, int BB>
+__global__ void __launch_bounds__(512)
+k_sweep_soa_diag(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
+                 const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx,
+                 int ny, int nz, int64_t stride, Collide<typename ST::R> k, DiagArgs d) {
+  using R = typename ST::R;
+  double acc[M_COUNT];
+#pragma unroll
+  for (int s = 0; s < M_COUNT; ++s) acc[s] = 0.0;
+  const int64_t N = (int64_t)nx * ny * nz;
+  const int row = blockIdx.x;
+  const int y = row % ny;
+  const int z = row / ny;
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+  for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int n = x + nx * row;
+    uint32_t lk = 0;
+    bool solid;
+    if (BB == LBM_HALFWAY) {
+      lk = links[n];
+      solid = (lk & 1u) != 0;
+      if (solid) continue;
+    } else {
+      solid = mask[n] != 0;
+    }
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int sx = Vel::cx[i] == 1 ? xm : (Vel::cx[i] == -1 ? xp : x);
+      const int sy = Vel::cy[i] == 1 ? ym : (Vel::cy[i] == -1 ? yp : y);
+      const int sz = Vel::cz[i] == 1 ? zm : (Vel::cz[i] == -1 ? zp : z);
+      int64_t at = (int64_t)i * stride + (sx + nx * (sy + ny * sz));
+      if (BB == LBM_HALFWAY && i != 0 && ((lk >> i) & 1u)) at = (int64_t)Vel::opp[i] * stride + n;
+      f[i] = ST::load(src[at], k.inv_scale);
+    }
+    diag_node<ST>(f, !solid, n, N, d, acc);
+    SrStream rs((uint32_t)n, k.step, ST::kStochastic);
+    if (BB == LBM_FULLWAY && solid) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        __builtin_nontemporal_store(ST::store(f[Vel::opp[i]], k.scale, rs.next()),
+                                    &dst[(int64_t)i * stride + n]);
+      continue;
+    }
+    trt_collide<R, ST::kShifted>(f, k);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      __builtin_nontemporal_store(ST::store(f[i], k.scale, rs.next()), &dst[(int64_t)i * stride + n]);
+  }
+  block_reduce<M_COUNT>(acc, 1u << M_UMAX);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int s = 0; s < M_COUNT; ++s) d.partials[(int64_t)blockIdx.x * kStatSlots + s] = acc[s];
+  }
+}
+
 template <class ST>
 __global__ void __launch_bounds__(1024)
 k_sweep_list(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
@@ -116,6 +219,39 @@ hipError_t launch_pull(lbm_ctx* c, const void* src, void* dst) {
     else
       hipLaunchKernelGGL((k_sweep_soa<ST, LBM_HALFWAY>), grid, block, lds, c->stream, s, d,
                          c->b.mask, c->b.links, p.nx, p.ny, p.nz, c->s.stride, k);
+    return hipGetLastError();
+  });
+}
+
+// The one-step pull over SoA direct addressing with fused diagnostics;
+// *rows receives the number of partial records written.
+hipError_t launch_pull_diag(lbm_ctx* c, const void* src, void* dst, int residual_mode,
+                            double* partials, int64_t* rows) {
+  return with_storage(c->p, [&](auto st) -> hipError_t {
+    using ST = decltype(st);
+    using T = typename ST::T;
+    const lbm_params& p = c->p;
+    const auto k = make_collide<typename ST::R>(p, c->step);
+    DiagArgs d;
+    d.gx = p.g[0];
+    d.gy = p.g[1];
+    d.gz = p.g[2];
+    d.u_prev = c->b.u_prev;
+    d.residual_mode = residual_mode;
+    d.partials = partials;
+    *rows = (int64_t)p.ny * p.nz;
+    int blk = row_block(c);
+    if (blk > 512) blk = 512;
+    const dim3 grid((unsigned)p.ny * (unsigned)p.nz), block(blk);
+    const size_t lds = sweep_lds(c, 0);
+    if (p.bounce == LBM_FULLWAY)
+      hipLaunchKernelGGL((k_sweep_soa_diag<ST, LBM_FULLWAY>), grid, block, lds, c->stream,
+                         (const T*)src, (T*)dst, c->b.mask, c->b.links, p.nx, p.ny, p.nz,
+                         c->s.stride, k, d);
+    else
+      hipLaunchKernelGGL((k_sweep_soa_diag<ST, LBM_HALFWAY>), grid, block, lds, c->stream,
+                         (const T*)src, (T*)dst, c->b.mask, c->b.links, p.nx, p.ny, p.nz,
+                         c->s.stride, k, d);
     return hipGetLastError();
   });
 }

@@ -74,6 +74,7 @@ class VerifyResult(ctypes.Structure):
 
 
 EXPORTED = ["lbm_plan", "lbm_init_geometry", "lbm_init_fields", "lbm_step", "lbm_macroscopic",
+            "lbm_step_diag",
             "lbm_verify", "lbm_export_pdfs", "lbm_import_pdfs", "lbm_get_sizes",
             "lbm_step_count", "lbm_current_buffer", "lbm_destroy", "lbm_strerror",
             "lbm_last_error", "lbm_membench"]
@@ -114,6 +115,7 @@ def load(path: str = LIB_PATH):
     lib.lbm_init_fields.argtypes = [vp, vp, vp]
     lib.lbm_step.argtypes = [vp, ctypes.c_int32]
     lib.lbm_macroscopic.argtypes = [vp, vp, vp, P(Stats)]
+    lib.lbm_step_diag.argtypes = [vp, P(Stats)]
     lib.lbm_verify.argtypes = [vp, ctypes.c_int32, vp, P(VerifyResult)]
     lib.lbm_export_pdfs.argtypes = [vp, vp, ctypes.c_int64, vp]
     lib.lbm_import_pdfs.argtypes = [vp, vp]
@@ -130,8 +132,8 @@ def load(path: str = LIB_PATH):
     lib.lbm_membench.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int64, ctypes.c_int64,
                                  ctypes.c_int32, vp]
     for name in ("lbm_plan", "lbm_init_geometry", "lbm_init_fields", "lbm_step",
-                 "lbm_macroscopic", "lbm_verify", "lbm_export_pdfs", "lbm_import_pdfs",
-                 "lbm_get_sizes", "lbm_current_buffer", "lbm_membench"):
+                 "lbm_macroscopic", "lbm_step_diag", "lbm_verify", "lbm_export_pdfs",
+                 "lbm_import_pdfs", "lbm_get_sizes", "lbm_current_buffer", "lbm_membench"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -264,6 +266,17 @@ class Lattice:
             out["rho"] = rho
             out["u"] = u.view(3, self.n_nodes)
         return out
+
+    def step_diag(self, allow_nonfinite: bool = False):
+        """One update plus the diagnostics of the state it starts from (the
+        ``macroscopic()`` dictionary without fields), in one fused sweep
+        where the form allows it."""
+        st = Stats()
+        rc = load().lbm_step_diag(self.ctx, ctypes.byref(st))
+        if not (allow_nonfinite and rc == ENONFINITE):
+            _check(rc, "lbm_step_diag")
+        return {"mass": st.mass, "momentum": list(st.momentum), "u_max": st.u_max,
+                "residual": st.residual, "nonfinite": st.nonfinite, "step": st.step, "rc": rc}
 
     def run_to_steady(self, tol: float, check_every: int = 100, max_steps: int = 1_000_000,
                       plateau_checks: int = 0):

@@ -234,6 +234,70 @@ def test_nonfinite_detected(L):
     assert st["rc"] == L.ENONFINITE and st["nonfinite"] >= 1
 
 
+_DIAG_FORMS = [
+    {"bounce": "fullway"}, {"bounce": "halfway"},
+    {"bounce": "fullway", "storage": "f32s"}, {"bounce": "halfway", "storage": "f16sr"},
+    # forms without a fused sweep run the two passes in turn
+    {"layout": "aos", "bounce": "halfway"}, {"addressing": "list", "bounce": "halfway"},
+    {"propagation": "aa", "bounce": "fullway"}, {"propagation": "push", "bounce": "halfway"},
+]
+
+
+@pytest.mark.parametrize("kw", _DIAG_FORMS)
+@pytest.mark.parametrize("shape", [(70, 9, 11), (5, 72, 64)])
+def test_step_diag_matches_separate_passes(L, kw, shape):
+    """lbm_step_diag = lbm_macroscopic then lbm_step(1): the same stats
+    (sums to FP64 rounding of a different fixed order; max |u| and the count
+    exactly) and the same state; the rows of (5, 72, 64) exceed one
+    reduction stage.  FP64 states also match the oracle."""
+    mask = I.random_solid_mask(*shape, seed=21, fraction=0.15)
+    bounce = kw["bounce"]
+    f0 = random_state(mask, seed=8, amplitude=0.02, bounce=bounce)
+    phys = dict(tau_plus=0.7, magic=3 / 16, g=(2e-5, -1e-5, 3e-6))
+    fused = L.Lattice(mask, **phys, **kw)
+    plain = L.Lattice(mask, **phys, **kw)
+    fused.import_(f0)
+    plain.import_(f0)
+    steps = 5
+    for k in range(steps):
+        a = fused.step_diag()
+        b = plain.macroscopic()
+        plain.step(1)
+        assert a["step"] == b["step"] == k
+        assert abs(a["mass"] - b["mass"]) <= 1e-13 * abs(b["mass"])
+        np.testing.assert_allclose(a["momentum"], b["momentum"], rtol=0, atol=1e-14 * b["mass"])
+        assert a["u_max"] == pytest.approx(b["u_max"], rel=1e-15, abs=0)
+        assert a["nonfinite"] == b["nonfinite"] == 0
+        if k == 0:
+            assert a["residual"] == b["residual"] == -1.0
+        else:
+            assert b["residual"] > 0
+            assert a["residual"] == pytest.approx(b["residual"], rel=1e-12)
+    assert fused.step_count == plain.step_count == steps
+    got, want = fused.export(), plain.export()
+    assert rel_maxabs(got, want) <= 1e-15
+    # both histories now hold the velocity of step steps - 1: one more pair
+    a = fused.step_diag()
+    b = plain.macroscopic()
+    assert a["residual"] == pytest.approx(b["residual"], rel=1e-12)
+    if kw.get("storage", "f64") == "f64":
+        ref = O.run(mask, f0, steps, phys["tau_plus"], phys["magic"], phys["g"], BOUNCE[bounce])
+        assert rel_maxabs(got, ref) <= TOL
+
+
+def test_step_diag_nonfinite(L):
+    """A non-finite population in the state the fused sweep reads is
+    counted and reported; the update has still run."""
+    mask = I.channel_mask(8, 6, 6)
+    lat = L.Lattice(mask)
+    f = O.rest_state(mask, 0)
+    f[2 + 8 * (2 + 6 * 2), 3] = np.nan
+    lat.import_(f)
+    st = lat.step_diag(allow_nonfinite=True)
+    assert st["rc"] == L.ENONFINITE and st["nonfinite"] == 1 and st["step"] == 0
+    assert lat.step_count == 1
+
+
 @pytest.mark.parametrize("kw", [{"addressing": "list", "bounce": "halfway"},
                                 {"layout": "aos", "bounce": "fullway"},
                                 {"storage": "f32s"}])
