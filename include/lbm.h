@@ -119,7 +119,9 @@ typedef struct {
   int32_t f16_scale_log2;   /* s for the F16 storages, 0..24; else ignored */
   int32_t block;            /* threads per workgroup, 0 = default; a
                                multiple of 64 up to 1024 (the AA kernels
-                               take at most 512 and cut larger values)     */
+                               take at most 512 and cut larger values; the
+                               AoS one-step pull always runs 32 x 8-node
+                               columns of 256 threads)                     */
   int32_t pad;              /* extra elements between direction arrays
                                (SOA/LIST); -1 = automatic                  */
   int32_t cu_slots;         /* at most this many sweep workgroups per
@@ -196,7 +198,8 @@ typedef struct lbm_ctx lbm_ctx;
 /* Sizes of every buffer for a parameter set and a host mask (N bytes).
  * Counts fluid nodes (and, for LIST_RIA, the runs); validates parameters
  * (tau+ > 1/2, Lambda > 0, dims >= 1 and <= 65535 on y and z, N < 2^31,
- * the lists need every population slot index below 2^31).  Allocates nothing.
+ * the lists need every population slot index below 2^31, the AoS one-step
+ * pull needs 19*nx*ny < 2^31).  Allocates nothing.
  * Errors: EINVAL, EOVERFLOW. */
 int lbm_plan(const lbm_params* params, const uint8_t* mask_host, lbm_sizes* out);
 

@@ -72,6 +72,11 @@ static int validate(const lbm_params* p) {
   }
   if (p->pad < -1 || p->pad > (1 << 24)) { set_error("pad must be -1 or in [0, 2^24]"); return LBM_EINVAL; }
   if (p->cu_slots < 0 || p->cu_slots > 64) { set_error("cu_slots must be in [0, 64]"); return LBM_EINVAL; }
+  if (p->layout == LBM_AOS && p->addressing == LBM_DIRECT && p->propagation == LBM_OS &&
+      (int64_t)p->nx * p->ny * Q > 0x7fffffffLL) {
+    set_error("the AoS one-step pull needs nx*ny*19 < 2^31 (one layer's populations)");
+    return LBM_EOVERFLOW;
+  }
   if (p->propagation != LBM_OS && p->propagation != LBM_AA && p->propagation != LBM_OS_PUSH) {
     set_error("bad propagation");
     return LBM_EINVAL;

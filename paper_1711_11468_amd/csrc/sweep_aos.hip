@@ -1,81 +1,197 @@
 // sweep_aos.hip - the one-step pull update for the AoS layout (Sect. 3,
 // "One Step Kernels"; node records of 19 values, compared with SoA in
 // Sect. 4.2).  Records are contiguous, so a wavefront reading one direction
-// of 64 nodes would touch 64 records; the kernel moves whole records between
-// HBM and LDS with contiguous loads and stores instead.
+// of 64 nodes would touch 64 records; the kernel instead reads each source
+// layer once, as whole records, and redistributes it through LDS.
+//
+// A workgroup owns a column of TY x BX nodes (rows y0.., nodes x0..) and
+// marches it through the layers zb .. ze-1 of its z chunk.  Each source
+// layer is read over the column and its one-node halo with contiguous
+// loads, and its populations are sorted by the layer they stream to:
+//   c_z = -1 (5 directions): needed by the output layer below, right away;
+//   c_z =  0 (9 directions): needed by the output layer itself, next step;
+//   c_z = +1 (5 directions): needed by the output layer above, in two steps.
+// LDS holds one region per class ("down", "level" and two alternating "up"
+// regions), each storing its populations position by position over the
+// halo'd column.  The next source layer is loaded into registers while the
+// current layer is collided and stored.  A thread's staged elements are
+// enumerated class by class, element e of a class being direction e % n_c
+// at halo position e / n_c, so a register slot's class is known at compile
+// time and its LDS slot is the thread index plus a constant.
+//
+// Results are stored straight from registers: each of the 19 store
+// instructions of a wavefront covers one slot of 64 records, and together
+// they write 64 whole contiguous records, which L2 assembles into full
+// lines (on MI355X this beat staging the records through LDS, and
+// non-temporal stores, which bypass that assembly, were 4.6x slower).
+// Columns of 32 x 8 nodes: 1.33x the algorithmic reads for the halo, 68 KB
+// of LDS in FP64, two workgroups per compute unit.
 #include "launch.hpp"
 
 namespace lbm {
 
-// AoS tile kernel.  A workgroup owns TY consecutive rows (y0 .. y0+TY-1) of
-// one z-layer and walks them in x-segments of BX nodes.  The pull sources of
-// that tile are the rows y0-1 .. y0+TY of the layers z, z-1 and z+1; each is
-// staged once, whole records, into LDS with contiguous loads, and every
-// thread takes from it the directions whose source it is for its own row
-// (a staged row supplies up to three output rows).  Results leave through
-// LDS again, one output row at a time, as contiguous runs of records.
-template <class ST, int BB>
-__global__ void __launch_bounds__(1024)
+// Population classes of the z march (c = c_z + 1) and the column shape.
+namespace zmarch {
+
+// Direction d of class c (c = c_z + 1), in velocity order.
+__host__ __device__ constexpr int dir_of(int c, int d) {
+  for (int i = 0; i < Q; ++i)
+    if (Vel::cz[i] + 1 == c && d-- == 0) return i;
+  return -1;
+}
+__host__ __device__ constexpr int count_of(int c) {
+  int n = 0;
+  for (int i = 0; i < Q; ++i) n += Vel::cz[i] + 1 == c ? 1 : 0;
+  return n;
+}
+// The directions of class c packed 5 bits each (for a runtime d).
+__host__ __device__ constexpr uint64_t packed_dirs(int c) {
+  uint64_t v = 0;
+  for (int d = 0; d < count_of(c); ++d) v |= (uint64_t)dir_of(c, d) << (5 * d);
+  return v;
+}
+__host__ __device__ constexpr int idx_of(int i) {
+  int n = 0;
+  for (int j = 0; j < i; ++j) n += Vel::cz[j] == Vel::cz[i] ? 1 : 0;
+  return n;
+}
+
+template <int BX, int TY>
+struct Shape {
+  static constexpr int NT = BX * TY, HX = BX + 2, HY = TY + 2, P = HX * HY;
+  // register slots per class (the last one padded) and LDS regions
+  static constexpr int K0 = (count_of(0) * P + NT - 1) / NT;
+  static constexpr int K1 = (count_of(1) * P + NT - 1) / NT;
+  static constexpr int K2 = (count_of(2) * P + NT - 1) / NT;
+  static constexpr int KE = K0 + K1 + K2;
+  static constexpr int D0 = 0, D1 = K0 * NT, D2 = (K0 + K1) * NT;  // up set p at D2 + p*K2*NT
+  static constexpr int STAGE = (K0 + K1 + 2 * K2) * NT;
+};
+
+template <int BX, int TY, class T>
+constexpr size_t lds_bytes() {
+  return (size_t)Shape<BX, TY>::STAGE * sizeof(T);
+}
+
+}  // namespace zmarch
+
+template <class ST, int BB, int BX, int TY>
+__global__ void __launch_bounds__(BX * TY)
 k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
-            const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx,
-            int ny, int nz, int BX, Collide<typename ST::R> k) {
+            const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx, int ny,
+            int nz, int zc, int n_tiles, Collide<typename ST::R> k) {
   using T = typename ST::T;
   using R = typename ST::R;
+  using S = zmarch::Shape<BX, TY>;
+  constexpr int NT = S::NT, HX = S::HX, P = S::P, K0 = S::K0, K1 = S::K1, K2 = S::K2, KE = S::KE;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* sm = reinterpret_cast<T*>(lds_raw);
-  const int TY = blockDim.x / BX;
+  T* L = reinterpret_cast<T*>(lds_raw);
+
+  // workgroup b runs on XCD b % 8: give each XCD a contiguous range of
+  // columns so that neighbouring columns share their halo lines in one L2
+  const int per = gridDim.x / 8;
+  const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tile >= n_tiles) return;
+  const int tiles_x = (nx + BX - 1) / BX, tiles_y = (ny + TY - 1) / TY;
+  const int tx_t = tile % tiles_x;
+  const int ty_t = (tile / tiles_x) % tiles_y;
+  const int zb = (tile / tiles_x / tiles_y) * zc;
+  const int ze = zb + zc < nz ? zb + zc : nz;
+  const int x0 = tx_t * BX, y0 = ty_t * TY;
+  const int seg = nx - x0 < BX ? nx - x0 : BX;
+  const int segy = ny - y0 < TY ? ny - y0 : TY;
   const int t = threadIdx.x, tx = t % BX, ty = t / BX;
-  const int tiles_y = (ny + TY - 1) / TY;
-  const int z = blockIdx.x / tiles_y;
-  const int y0 = (blockIdx.x - z * tiles_y) * TY;
-  const int y = y0 + ty;
-  for (int x0 = 0; x0 < nx; x0 += BX) {
-    const int seg = nx - x0 < BX ? nx - x0 : BX;
-    const bool active = y < ny && tx < seg;
-    R f[Q];
+  const bool active = tx < seg && ty < segy;
+  const int64_t layer = (int64_t)nx * ny * Q;
+
+  // goff: offset inside a layer of staged element j (below 2^31: the plan
+  // rejects larger layers for this form).  Positions past the
+  // column's real extent repeat the last real one; the padding elements of
+  // a class repeat its last element (their LDS slots are never read).
+  uint32_t goff[KE];
+  auto setup = [&](int j, int c, int e_raw) {
+    const int nd = zmarch::count_of(c), n_c = nd * P;
+    const int e = e_raw < n_c ? e_raw : n_c - 1;
+    const int pp = e / nd, d = e - pp * nd;
+    const int hy = pp / HX, hx = pp - hy * HX;
+    int xs = x0 - 1 + (hx < seg + 1 ? hx : seg + 1);
+    int ys = y0 - 1 + (hy < segy + 1 ? hy : segy + 1);
+    xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+    ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+    const int i = (int)((zmarch::packed_dirs(c) >> (5 * d)) & 31);
+    goff[j] = (uint32_t)((ys * nx + xs) * Q + i);
+  };
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = R(0);
+  for (int j = 0; j < K0; ++j) setup(j, 0, t + j * NT);
 #pragma unroll
-    for (int zz = 0; zz < 3; ++zz) {
-      const int dz = zz == 0 ? 0 : (zz == 1 ? 1 : -1);  // c_z supplied by this layer
-      int sz = z - dz;
-      sz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
-      for (int sr = -1; sr <= TY; ++sr) {
-        const int sy = ((y0 + sr) % ny + ny) % ny;
-        const int64_t rbase = ((int64_t)sy + (int64_t)ny * sz) * nx;
-        const int nrec = seg + 2;  // records x0-1 .. x0+seg
-        __syncthreads();
-        for (int e = t; e < nrec * Q; e += blockDim.x) {
-          const int rr = e / Q;
-          const int i = e - rr * Q;
-          int xs = x0 - 1 + rr;
-          xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-          sm[e] = src[(rbase + xs) * Q + i];
-        }
-        __syncthreads();
-        if (active) {
-          const int cy_req = ty - sr;  // y - c_y = y0 + sr
+  for (int j = 0; j < K1; ++j) setup(K0 + j, 1, t + j * NT);
 #pragma unroll
-          for (int i = 0; i < Q; ++i) {
-            if (Vel::cz[i] != dz) continue;
-            if (Vel::cy[i] == cy_req) f[i] = ST::load(sm[(tx + 1 - Vel::cx[i]) * Q + i], k.inv_scale);
-          }
-        }
+  for (int j = 0; j < K2; ++j) setup(K0 + K1 + j, 2, t + j * NT);
+  auto wrapz = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+  T r[KE];
+  auto load_layer = [&](int z) {
+    const T* base = src + (int64_t)wrapz(z) * layer;
+#pragma unroll
+    for (int j = 0; j < KE; ++j) r[j] = base[goff[j]];
+  };
+  T* const Lt = L + t;
+  auto put_up = [&](int par) {
+#pragma unroll
+    for (int j = 0; j < K2; ++j) Lt[S::D2 + par * K2 * NT + j * NT] = r[K0 + K1 + j];
+  };
+  auto put_level = [&]() {
+#pragma unroll
+    for (int j = 0; j < K1; ++j) Lt[S::D1 + j * NT] = r[K0 + j];
+  };
+
+  // prologue: up populations of layer zb-1 (set 0), level and up of zb (set 1)
+  load_layer(zb - 1);
+  put_up(0);
+  load_layer(zb);
+  put_level();
+  put_up(1);
+  load_layer(zb + 1);
+  const int me = (ty + 1) * HX + tx + 1;
+  for (int z = zb; z < ze; ++z) {
+    const int s = z - zb;
+    const int64_t n = ((int64_t)z * ny + y0 + ty) * nx + x0 + tx;
+    uint32_t lk = 0;
+    bool solid = false;
+    if (active) {
+      if (BB == LBM_HALFWAY) {
+        lk = links[n];
+        solid = (lk & 1u) != 0;
+      } else {
+        solid = mask[n] != 0;
       }
     }
-    const int64_t n = ((int64_t)y + (int64_t)ny * z) * nx + x0 + tx;
+#pragma unroll
+    for (int j = 0; j < K0; ++j) Lt[S::D0 + j * NT] = r[j];  // down of layer z+1
+    __syncthreads();
+    R f[Q];
     if (active) {
-      bool solid;
+      const T* up = L + S::D2 + (s & 1) * K2 * NT;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int c = Vel::cz[i] + 1, nd = zmarch::count_of(c);
+        const int pos = me - Vel::cy[i] * HX - Vel::cx[i];
+        const T* reg = c == 0 ? L + S::D0 : (c == 1 ? L + S::D1 : up);
+        f[i] = ST::load(reg[pos * nd + zmarch::idx_of(i)], k.inv_scale);
+      }
+    }
+    __syncthreads();
+    // layer z+1: level (used at step s+1), up into the set that held layer
+    // z-1 (used at step s+2); then start loading layer z+2
+    put_level();
+    put_up(s & 1);
+    if (z + 1 < ze) load_layer(z + 2);
+    if (active) {
       if (BB == LBM_HALFWAY) {
-        const uint32_t lk = links[n];
-        solid = (lk & 1u) != 0;
         if (!solid && (lk >> 1)) {
 #pragma unroll
           for (int i = 1; i < Q; ++i)
             if ((lk >> i) & 1u) f[i] = ST::load(src[n * Q + Vel::opp[i]], k.inv_scale);
         }
-      } else {
-        solid = mask[n] != 0;
       }
       if (!solid) {
         trt_collide<R, ST::kShifted>(f, k);
@@ -86,55 +202,47 @@ k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[i] = g[i];
       } else {
-        // half-way solids hold no state; keep their slots at the rest value
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[i] = ST::kShifted ? R(0) : R(weight(i));
       }
-    }
-    for (int w = 0; w < TY; ++w) {
-      __syncthreads();
-      if (active && ty == w) {
-        SrStream rs((uint32_t)n, k.step, ST::kStochastic);
+      SrStream rs((uint32_t)n, k.step, ST::kStochastic);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) sm[tx * Q + i] = ST::store(f[i], k.scale, rs.next());
-      }
-      __syncthreads();
-      if (y0 + w < ny) {
-        T* out = dst + (((int64_t)(y0 + w) + (int64_t)ny * z) * nx + x0) * Q;
-        for (int e = t; e < seg * Q; e += blockDim.x) __builtin_nontemporal_store(sm[e], &out[e]);
-      }
+      for (int i = 0; i < Q; ++i) dst[n * Q + i] = ST::store(f[i], k.scale, rs.next());
     }
   }
 }
 
-size_t aos_lds_bytes(const lbm_ctx* c, int bx) {
-  const int es = c->p.storage == LBM_F64 ? 8 : (c->p.storage == LBM_F32_SHIFTED ? 4 : 2);  // F16: 2
-  return (size_t)(bx + 2) * Q * es;
-}
+constexpr int kAosBX = 32, kAosTY = 8;
 
 hipError_t launch_pull_aos(lbm_ctx* c, const void* src, void* dst) {
   return with_storage(c->p, [&](auto st) -> hipError_t {
     using ST = decltype(st);
     using T = typename ST::T;
+    constexpr int BX = kAosBX, TY = kAosTY;
     const lbm_params& p = c->p;
     const auto k = make_collide<typename ST::R>(p, c->step);
-    const T* s = (const T*)src;
-    T* d = (T*)dst;
-    // tiles of TY rows x BX nodes: BX = min(128, nx rounded to 64), TY =
-    // workgroup size / BX
-    const int nx_r = ((p.nx + 63) / 64) * 64;
-    const int bx = nx_r < 128 ? nx_r : 128;
-    int wg = c->block < bx ? bx : c->block;
-    wg = wg / bx * bx;
-    const int ty = wg / bx;
-    const dim3 tgrid((unsigned)((p.ny + ty - 1) / ty) * (unsigned)p.nz), tblock(wg);
-    const size_t lds = sweep_lds(c, aos_lds_bytes(c, bx));
+    const int tiles_x = (p.nx + BX - 1) / BX, tiles_y = (p.ny + TY - 1) / TY;
+    const int64_t cols = (int64_t)tiles_x * tiles_y;
+    // z chunks: about 8192 workgroups (16 rounds of two per compute unit
+    // measured better than fewer, longer marches), chunks of at least 32
+    // layers (each chunk reads two extra layers), split evenly
+    int64_t nzc = (8192 + cols - 1) / cols;
+    const int64_t max_chunks = (p.nz + 31) / 32;
+    if (nzc > max_chunks) nzc = max_chunks;
+    if (nzc < 1) nzc = 1;
+    const int zc = (int)((p.nz + nzc - 1) / nzc);
+    nzc = (p.nz + zc - 1) / zc;
+    const int n_tiles = (int)(cols * nzc);
+    const unsigned grid = (unsigned)((n_tiles + 7) / 8 * 8);  // whole rounds of the 8 XCDs
+    const size_t lds = sweep_lds(c, zmarch::lds_bytes<BX, TY, T>());
     if (p.bounce == LBM_FULLWAY)
-      hipLaunchKernelGGL((k_sweep_aos<ST, LBM_FULLWAY>), tgrid, tblock, lds, c->stream, s, d,
-                         c->b.mask, c->b.links, p.nx, p.ny, p.nz, bx, k);
+      hipLaunchKernelGGL((k_sweep_aos<ST, LBM_FULLWAY, BX, TY>), dim3(grid), dim3(BX * TY), lds,
+                         c->stream, (const T*)src, (T*)dst, c->b.mask, c->b.links, p.nx, p.ny,
+                         p.nz, zc, n_tiles, k);
     else
-      hipLaunchKernelGGL((k_sweep_aos<ST, LBM_HALFWAY>), tgrid, tblock, lds, c->stream, s, d,
-                         c->b.mask, c->b.links, p.nx, p.ny, p.nz, bx, k);
+      hipLaunchKernelGGL((k_sweep_aos<ST, LBM_HALFWAY, BX, TY>), dim3(grid), dim3(BX * TY), lds,
+                         c->stream, (const T*)src, (T*)dst, c->b.mask, c->b.links, p.nx, p.ny,
+                         p.nz, zc, n_tiles, k);
     return hipGetLastError();
   });
 }

@@ -92,6 +92,17 @@ def test_plan_overflow():
     assert b"32-bit" in lib.lbm_last_error() or b"too large" in lib.lbm_last_error()
 
 
+def test_plan_aos_pull_layer_limit():
+    """The AoS one-step pull addresses one layer's populations with 32-bit
+    offsets: layers of 19 * nx * ny >= 2^31 values are refused."""
+    lib = lbm.load()
+    p = lbm.make_params((1, 8192, 16384), layout="aos")  # 134 M nodes, 2.55e9 values per layer
+    s = lbm.Sizes()
+    tiny = np.zeros(1, dtype=np.uint8)  # not read: the check comes first
+    assert lib.lbm_plan(ctypes.byref(p), tiny.ctypes.data, ctypes.byref(s)) == lbm.EOVERFLOW
+    assert b"AoS one-step pull" in lib.lbm_last_error()
+
+
 def test_null_arguments_rejected():
     lib = lbm.load()
     assert lib.lbm_step(None, 1) == lbm.EINVAL

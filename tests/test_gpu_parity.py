@@ -55,11 +55,12 @@ def test_channel_64x32x32_200_steps_soa(L):
 
 @pytest.mark.parametrize("layout,bounce", [("soa", "fullway"), ("soa", "halfway"),
                                            ("aos", "fullway"), ("aos", "halfway")])
-@pytest.mark.parametrize("shape", [(9, 10, 12), (5, 7, 131)])
+@pytest.mark.parametrize("shape", [(9, 10, 12), (5, 7, 131), (100, 21, 45)])
 def test_direct_random_state(L, layout, bounce, shape):
     """Random solids (~20 %), random populations and a 3-component force:
     any index or sign error shows.  (5, 7, 131): rows longer than one
-    workgroup pass with a ragged tail."""
+    workgroup pass with a ragged tail.  (100, 21, 45): the AoS sweep's
+    32 x 8 columns end ragged in x and y and march four z chunks."""
     nz, ny, nx = shape
     mask = I.random_solid_mask(nx, ny, nz, seed=3, fraction=0.2)
     f0 = random_state(mask, seed=9, amplitude=0.02, bounce=bounce)
