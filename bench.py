@@ -270,7 +270,8 @@ def main():
                          ("soa_f16_shifted_stochastic", dict(storage="f16sr")),
                          ("soa_f64_halfway", dict(bounce="halfway")),
                          ("aa_soa_f64", dict(propagation="aa")),
-                         ("push_soa_f64", dict(propagation="push"))]:
+                         ("push_soa_f64", dict(propagation="push")),
+                         ("push_aos_f64", dict(propagation="push", layout="aos"))]:
             log("variant %s" % name)
             lat, r = run_variant(mask, args.steps, args.warmup, **kw)
             variants[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}

@@ -120,8 +120,8 @@ typedef struct {
   int32_t block;            /* threads per workgroup, 0 = default; a
                                multiple of 64 up to 1024 (the AA kernels
                                take at most 512 and cut larger values; the
-                               AoS one-step pull always runs 32 x 8-node
-                               columns of 256 threads)                     */
+                               AoS one-step pull and push always run their
+                               own column shapes)                          */
   int32_t pad;              /* extra elements between direction arrays
                                (SOA/LIST); -1 = automatic                  */
   int32_t cu_slots;         /* at most this many sweep workgroups per

@@ -25,7 +25,8 @@
 // lines (on MI355X this beat staging the records through LDS, and
 // non-temporal stores, which bypass that assembly, were 4.6x slower).
 // Columns of 32 x 8 nodes: 1.33x the algorithmic reads for the halo, 68 KB
-// of LDS in FP64, two workgroups per compute unit.
+// of LDS in FP64, two workgroups per compute unit.  The one-step push over
+// AoS records (below) runs the same march.
 #include "launch.hpp"
 
 namespace lbm {
@@ -212,6 +213,188 @@ k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__
   }
 }
 
+// Launch grid of a z march over BX x TY columns: about 8192 workgroups
+// (16 rounds of two per compute unit measured better than fewer, longer
+// marches), z chunks of at least 32 layers (each chunk reads two extra
+// layers) split evenly, the grid padded to whole rounds of the 8 XCDs.
+static void march_grid(const lbm_params& p, int BX, int TY, int& zc, int& n_tiles,
+                       unsigned& grid) {
+  const int64_t cols = (int64_t)((p.nx + BX - 1) / BX) * ((p.ny + TY - 1) / TY);
+  int64_t nzc = (8192 + cols - 1) / cols;
+  const int64_t max_chunks = (p.nz + 31) / 32;
+  if (nzc > max_chunks) nzc = max_chunks;
+  if (nzc < 1) nzc = 1;
+  zc = (int)((p.nz + nzc - 1) / nzc);
+  nzc = (p.nz + zc - 1) / zc;
+  n_tiles = (int)(cols * nzc);
+  grid = (unsigned)((n_tiles + 7) / 8 * 8);
+}
+
+// ---- one-step push over AoS records ---------------------------------------
+// The push writes f*_i(x) into slot i of x + c_i (or, under half-way
+// bounce-back towards a solid node, into slot opp(i) of x).  Seen from the
+// destination y, slot i holds f*_i(y - c_i), so a column can produce whole
+// destination records if it also collides the nodes of its one-node halo:
+// the same z march as the pull, with the collision done on the source side
+// before the populations are sorted into the class regions.  One thread per
+// halo'd position: it loads that node's record (the 19 loads of a wavefront
+// cover consecutive whole records), collides it (rounding to the storage
+// format at the source, as the scattering kernel does), and the threads of
+// interior positions gather and store their destination records.  Under
+// half-way bounce-back a destination whose source y - c_i is solid takes
+// its own f*_opp(i), kept in registers from the step that collided it.
+template <int BX, int TY>
+struct PushShape {
+  static constexpr int HX = BX + 2, HY = TY + 2, P = HX * HY;
+  static constexpr int NT = (P + 63) / 64 * 64;
+  static constexpr int R0 = 0, R1 = 5 * P, R2 = 14 * P;  // down, level, up set 0 (set 1 at R2 + 5P)
+  static constexpr int STAGE = 24 * P;
+};
+
+template <class ST, int BB, int BX, int TY>
+__global__ void __launch_bounds__((PushShape<BX, TY>::NT))
+k_push_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
+           const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx, int ny,
+           int nz, int zc, int n_tiles, Collide<typename ST::R> k) {
+  using T = typename ST::T;
+  using R = typename ST::R;
+  using S = PushShape<BX, TY>;
+  constexpr int HX = S::HX, P = S::P;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* L = reinterpret_cast<T*>(lds_raw);
+
+  const int per = gridDim.x / 8;
+  const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tile >= n_tiles) return;
+  const int tiles_x = (nx + BX - 1) / BX, tiles_y = (ny + TY - 1) / TY;
+  const int tx_t = tile % tiles_x;
+  const int ty_t = (tile / tiles_x) % tiles_y;
+  const int zb = (tile / tiles_x / tiles_y) * zc;
+  const int ze = zb + zc < nz ? zb + zc : nz;
+  const int x0 = tx_t * BX, y0 = ty_t * TY;
+  const int seg = nx - x0 < BX ? nx - x0 : BX;
+  const int segy = ny - y0 < TY ? ny - y0 : TY;
+  const int t = threadIdx.x;
+  const bool live = t < P;
+  const int pt = live ? t : P - 1;
+  const int hy = pt / HX, hx = pt - hy * HX;
+  const bool interior = live && hx >= 1 && hx <= seg && hy >= 1 && hy <= segy;
+  int xs = x0 - 1 + (hx < seg + 1 ? hx : seg + 1);
+  int ys = y0 - 1 + (hy < segy + 1 ? hy : segy + 1);
+  xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+  ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+  const int64_t plane_nodes = (int64_t)nx * ny;
+  const int64_t col = (int64_t)ys * nx + xs;
+  auto wrapz = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+
+  T r[Q];
+  uint32_t geo_next = 0;  // link word (half-way) or flag byte of the loaded node
+  auto load = [&](int z) {
+    const int64_t node = wrapz(z) * plane_nodes + col;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) r[i] = src[node * Q + i];
+    geo_next = BB == LBM_HALFWAY ? links[node] : (uint32_t)mask[node];
+  };
+  T g[Q];
+  auto collide_src = [&](int z) {
+    const bool solid = BB == LBM_HALFWAY ? (geo_next & 1u) != 0 : geo_next != 0;
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = ST::load(r[i], k.inv_scale);
+    if (!solid) {
+      trt_collide<R, ST::kShifted>(f, k);
+    } else if (BB == LBM_FULLWAY) {
+      R h[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) h[i] = f[Vel::opp[i]];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] = h[i];
+    }
+    SrStream rs((uint32_t)(wrapz(z) * plane_nodes + col), k.step, ST::kStochastic);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = ST::store(f[i], k.scale, rs.next());
+  };
+  // class c of g into its region (up: set par) at this thread's position
+  auto put = [&](int c, int par) {
+    if (!live) return;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (Vel::cz[i] + 1 != c) continue;
+      const int nd = zmarch::count_of(c);
+      const int base = c == 0 ? S::R0 : (c == 1 ? S::R1 : S::R2 + par * 5 * P);
+      L[base + t * nd + zmarch::idx_of(i)] = g[i];
+    }
+  };
+
+  T gprev[BB == LBM_HALFWAY ? Q : 1];
+  uint32_t geo_cur = 0;
+  // Step s collides source layer z+1 = zb+s+1; steps -2 and -1 only fill
+  // the regions (up of zb-1, level and up of zb), so that every collision
+  // runs through the same code.
+  load(zb - 1);
+  for (int s = -2; s < ze - zb; ++s) {
+    const int z = zb + s;
+    collide_src(z + 1);
+    if (s >= 0) {
+      put(0, 0);  // down populations of layer z+1
+      __syncthreads();
+      const bool store = interior && !(BB == LBM_HALFWAY && (geo_cur & 1u));
+      if (store) {
+        const int64_t n = (int64_t)z * plane_nodes + col;
+        const T* up = L + S::R2 + (s & 1) * 5 * P;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const int c = Vel::cz[i] + 1, nd = zmarch::count_of(c);
+          const int pos = t - Vel::cy[i] * HX - Vel::cx[i];
+          const T* reg = c == 0 ? L + S::R0 : (c == 1 ? L + S::R1 : up);
+          T v = reg[pos * nd + zmarch::idx_of(i)];
+          if (BB == LBM_HALFWAY && i != 0 && ((geo_cur >> i) & 1u)) v = gprev[Vel::opp[i]];
+          dst[n * Q + i] = v;
+        }
+      }
+      __syncthreads();
+    }
+    // level populations of layer z+1 (used at step s+1), up populations
+    // into the set that held layer z-1 (used at step s+2)
+    put(1, 0);
+    put(2, s & 1);
+    if (BB == LBM_HALFWAY) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) gprev[i] = g[i];
+    }
+    geo_cur = geo_next;
+    if (s + 1 < ze - zb) load(z + 2);
+  }
+}
+
+template <class ST, int BX, int TY>
+static hipError_t launch_push_aos_t(lbm_ctx* c, const void* src, void* dst) {
+  using T = typename ST::T;
+  const lbm_params& p = c->p;
+  const auto k = make_collide<typename ST::R>(p, c->step);
+  int zc, n_tiles;
+  unsigned grid;
+  march_grid(p, BX, TY, zc, n_tiles, grid);
+  using S = PushShape<BX, TY>;
+  const size_t lds = sweep_lds(c, (size_t)S::STAGE * sizeof(T));
+  if (p.bounce == LBM_FULLWAY)
+    hipLaunchKernelGGL((k_push_aos<ST, LBM_FULLWAY, BX, TY>), dim3(grid), dim3(S::NT), lds,
+                       c->stream, (const T*)src, (T*)dst, c->b.mask, c->b.links, p.nx, p.ny, p.nz,
+                       zc, n_tiles, k);
+  else
+    hipLaunchKernelGGL((k_push_aos<ST, LBM_HALFWAY, BX, TY>), dim3(grid), dim3(S::NT), lds,
+                       c->stream, (const T*)src, (T*)dst, c->b.mask, c->b.links, p.nx, p.ny, p.nz,
+                       zc, n_tiles, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_push_aos(lbm_ctx* c, const void* src, void* dst) {
+  return with_storage(c->p, [&](auto st) -> hipError_t {
+    using ST = decltype(st);
+    return launch_push_aos_t<ST, 32, 8>(c, src, dst);
+  });
+}
+
 constexpr int kAosBX = 32, kAosTY = 8;
 
 hipError_t launch_pull_aos(lbm_ctx* c, const void* src, void* dst) {
@@ -221,19 +404,9 @@ hipError_t launch_pull_aos(lbm_ctx* c, const void* src, void* dst) {
     constexpr int BX = kAosBX, TY = kAosTY;
     const lbm_params& p = c->p;
     const auto k = make_collide<typename ST::R>(p, c->step);
-    const int tiles_x = (p.nx + BX - 1) / BX, tiles_y = (p.ny + TY - 1) / TY;
-    const int64_t cols = (int64_t)tiles_x * tiles_y;
-    // z chunks: about 8192 workgroups (16 rounds of two per compute unit
-    // measured better than fewer, longer marches), chunks of at least 32
-    // layers (each chunk reads two extra layers), split evenly
-    int64_t nzc = (8192 + cols - 1) / cols;
-    const int64_t max_chunks = (p.nz + 31) / 32;
-    if (nzc > max_chunks) nzc = max_chunks;
-    if (nzc < 1) nzc = 1;
-    const int zc = (int)((p.nz + nzc - 1) / nzc);
-    nzc = (p.nz + zc - 1) / zc;
-    const int n_tiles = (int)(cols * nzc);
-    const unsigned grid = (unsigned)((n_tiles + 7) / 8 * 8);  // whole rounds of the 8 XCDs
+    int zc, n_tiles;
+    unsigned grid;
+    march_grid(p, BX, TY, zc, n_tiles, grid);
     const size_t lds = sweep_lds(c, zmarch::lds_bytes<BX, TY, T>());
     if (p.bounce == LBM_FULLWAY)
       hipLaunchKernelGGL((k_sweep_aos<ST, LBM_FULLWAY, BX, TY>), dim3(grid), dim3(BX * TY), lds,

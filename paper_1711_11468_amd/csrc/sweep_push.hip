@@ -1,5 +1,6 @@
 // sweep_push.hip - the one-step update, push flavour (Sect. 3, "One Step
-// Kernels"); direct addressing in SoA and AoS layout, list addressing.
+// Kernels"); direct addressing in SoA layout and list addressing.  The AoS
+// push runs as a z march of columns (sweep_aos.hip).
 #include "gather.hpp"
 #include "launch.hpp"
 
@@ -100,17 +101,13 @@ hipError_t launch_push(lbm_ctx* c, const void* src, void* dst) {
                          d, c->b.adj, nf, c->s.stride, k);
       return hipGetLastError();
     }
+    if (p.layout == LBM_AOS) return launch_push_aos(c, src, dst);
     const dim3 g((unsigned)p.ny * (unsigned)p.nz), b(row_block(c));
 #define LBM_PUSH_LAUNCH(LAY, BB)                                                                \
   hipLaunchKernelGGL((k_push_direct<ST, LAY, BB>), g, b, lds, c->stream, s, d, c->b.mask,     \
                      c->b.links, p.nx, p.ny, p.nz, c->s.stride, k)
-    if (p.layout == LBM_SOA) {
-      if (p.bounce == LBM_FULLWAY) LBM_PUSH_LAUNCH(LBM_SOA, LBM_FULLWAY);
-      else LBM_PUSH_LAUNCH(LBM_SOA, LBM_HALFWAY);
-    } else {
-      if (p.bounce == LBM_FULLWAY) LBM_PUSH_LAUNCH(LBM_AOS, LBM_FULLWAY);
-      else LBM_PUSH_LAUNCH(LBM_AOS, LBM_HALFWAY);
-    }
+    if (p.bounce == LBM_FULLWAY) LBM_PUSH_LAUNCH(LBM_SOA, LBM_FULLWAY);
+    else LBM_PUSH_LAUNCH(LBM_SOA, LBM_HALFWAY);
 #undef LBM_PUSH_LAUNCH
     return hipGetLastError();
   });
