@@ -48,6 +48,7 @@ inline void* pdf_buf(lbm_ctx* c, int which) { return which == 0 ? c->b.pdf_a : c
 hipError_t launch_pull(lbm_ctx* c, const void* src, void* dst);
 hipError_t launch_pull_aos(lbm_ctx* c, const void* src, void* dst);
 hipError_t launch_push_aos(lbm_ctx* c, const void* src, void* dst);
+hipError_t launch_aa_aos_odd(lbm_ctx* c, void* buf);
 hipError_t launch_push(lbm_ctx* c, const void* src, void* dst);
 hipError_t launch_aa(lbm_ctx* c, void* buf);
 // Fluid list in AoS records: pull, push and both AA steps.

@@ -1,6 +1,7 @@
 // sweep_aa.hip - the AA pattern (Sect. 3): one lattice updated in place by
 // alternating node-local (even) and neighbour (odd) kernels; direct
-// addressing in SoA and AoS layout, list addressing.
+// addressing in SoA and AoS layout, list addressing.  The AoS neighbour
+// step runs as a z march of columns (sweep_aos.hip).
 #include "gather.hpp"
 #include "launch.hpp"
 
@@ -125,6 +126,7 @@ hipError_t launch_aa(lbm_ctx* c, void* buf) {
       else hipLaunchKernelGGL((k_aa_list<ST, false>), g, b, lds, c->stream, A, c->b.adj, nf, c->s.stride, k);
       return hipGetLastError();
     }
+    if (odd && p.layout == LBM_AOS) return launch_aa_aos_odd(c, buf);  // z-marching columns
     const int rb = row_block(c);
     const dim3 g((unsigned)p.ny * (unsigned)p.nz), b(rb < kAaMaxBlock ? rb : kAaMaxBlock);
 #define LBM_AA_LAUNCH(LAY, BB, ODD)                                                              \

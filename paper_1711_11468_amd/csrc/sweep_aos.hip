@@ -45,10 +45,16 @@ __host__ __device__ constexpr int count_of(int c) {
   for (int i = 0; i < Q; ++i) n += Vel::cz[i] + 1 == c ? 1 : 0;
   return n;
 }
-// The directions of class c packed 5 bits each (for a runtime d).
+// The directions of class c packed 5 bits each (for a runtime d), and
+// their opposites.
 __host__ __device__ constexpr uint64_t packed_dirs(int c) {
   uint64_t v = 0;
   for (int d = 0; d < count_of(c); ++d) v |= (uint64_t)dir_of(c, d) << (5 * d);
+  return v;
+}
+__host__ __device__ constexpr uint64_t packed_opp_dirs(int c) {
+  uint64_t v = 0;
+  for (int d = 0; d < count_of(c); ++d) v |= (uint64_t)Vel::opp[dir_of(c, d)] << (5 * d);
   return v;
 }
 __host__ __device__ constexpr int idx_of(int i) {
@@ -76,11 +82,20 @@ constexpr size_t lds_bytes() {
 
 }  // namespace zmarch
 
-template <class ST, int BB, int BX, int TY>
-__global__ void __launch_bounds__(BX * TY)
-k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
-            const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx, int ny,
-            int nz, int zc, int n_tiles, Collide<typename ST::R> k) {
+// The march shared by the one-step pull (AA = false: read src, store whole
+// records into dst) and the AA neighbour step (AA = true: src == dst, the
+// lattice updated in place).  In the AA neighbour step node x reads slot
+// opp(i) of x - c_i and writes f*_i into slot i of x + c_i: the staged
+// slot of direction number d of a class is then opp(dir_of(c, d)), the
+// gather is the pull's, and the results go to the neighbours' slots one by
+// one (every slot is read and then written by the one node that owns it,
+// so staging whole records in place is safe: the slots of other nodes that
+// come along are never used).
+template <class ST, int BB, int BX, int TY, bool AA>
+__device__ __forceinline__ void aos_march(const typename ST::T* src, typename ST::T* dst,
+                                          const uint8_t* mask, const uint32_t* links, int nx,
+                                          int ny, int nz, int zc, int n_tiles,
+                                          const Collide<typename ST::R>& k) {
   using T = typename ST::T;
   using R = typename ST::R;
   using S = zmarch::Shape<BX, TY>;
@@ -119,7 +134,7 @@ k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__
     int ys = y0 - 1 + (hy < segy + 1 ? hy : segy + 1);
     xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
     ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-    const int i = (int)((zmarch::packed_dirs(c) >> (5 * d)) & 31);
+    const int i = (int)(((AA ? zmarch::packed_opp_dirs(c) : zmarch::packed_dirs(c)) >> (5 * d)) & 31);
     goff[j] = (uint32_t)((ys * nx + xs) * Q + i);
   };
 #pragma unroll
@@ -186,7 +201,33 @@ k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__
     put_level();
     put_up(s & 1);
     if (z + 1 < ze) load_layer(z + 2);
-    if (active) {
+    if (AA) {
+      // solid nodes hold no state the AA steps move (full-way reversal maps
+      // each slot onto itself)
+      if (active && !solid) {
+        if (BB == LBM_HALFWAY && (lk >> 1)) {
+#pragma unroll
+          for (int i = 1; i < Q; ++i)
+            if ((lk >> i) & 1u) f[i] = ST::load(src[n * Q + i], k.inv_scale);
+        }
+        trt_collide<R, ST::kShifted>(f, k);
+        const int x = x0 + tx, y = y0 + ty;
+        const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+        const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+        const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+        SrStream rs((uint32_t)n, k.step, ST::kStochastic);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const int ux = Vel::cx[i] == 1 ? xp : (Vel::cx[i] == -1 ? xm : x);
+          const int uy = Vel::cy[i] == 1 ? yp : (Vel::cy[i] == -1 ? ym : y);
+          const int uz = Vel::cz[i] == 1 ? zp : (Vel::cz[i] == -1 ? zm : z);
+          int64_t at = (((int64_t)uz * ny + uy) * nx + ux) * Q + i;
+          // link bit opp(i): x + c_i is solid, the population stays home
+          if (BB == LBM_HALFWAY && i != 0 && ((lk >> Vel::opp[i]) & 1u)) at = n * Q + Vel::opp[i];
+          dst[at] = ST::store(f[i], k.scale, rs.next());
+        }
+      }
+    } else if (active) {
       if (BB == LBM_HALFWAY) {
         if (!solid && (lk >> 1)) {
 #pragma unroll
@@ -211,6 +252,22 @@ k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__
       for (int i = 0; i < Q; ++i) dst[n * Q + i] = ST::store(f[i], k.scale, rs.next());
     }
   }
+}
+
+template <class ST, int BB, int BX, int TY>
+__global__ void __launch_bounds__(BX * TY)
+k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
+            const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx, int ny,
+            int nz, int zc, int n_tiles, Collide<typename ST::R> k) {
+  aos_march<ST, BB, BX, TY, false>(src, dst, mask, links, nx, ny, nz, zc, n_tiles, k);
+}
+
+template <class ST, int BB, int BX, int TY>
+__global__ void __launch_bounds__(BX * TY)
+k_aa_aos_odd(typename ST::T* A, const uint8_t* __restrict__ mask,
+             const uint32_t* __restrict__ links, int nx, int ny, int nz, int zc, int n_tiles,
+             Collide<typename ST::R> k) {
+  aos_march<ST, BB, BX, TY, true>(A, A, mask, links, nx, ny, nz, zc, n_tiles, k);
 }
 
 // Launch grid of a z march over BX x TY columns: about 8192 workgroups
@@ -416,6 +473,27 @@ hipError_t launch_pull_aos(lbm_ctx* c, const void* src, void* dst) {
       hipLaunchKernelGGL((k_sweep_aos<ST, LBM_HALFWAY, BX, TY>), dim3(grid), dim3(BX * TY), lds,
                          c->stream, (const T*)src, (T*)dst, c->b.mask, c->b.links, p.nx, p.ny,
                          p.nz, zc, n_tiles, k);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_aa_aos_odd(lbm_ctx* c, void* buf) {
+  return with_storage(c->p, [&](auto st) -> hipError_t {
+    using ST = decltype(st);
+    using T = typename ST::T;
+    constexpr int BX = kAosBX, TY = kAosTY;
+    const lbm_params& p = c->p;
+    const auto k = make_collide<typename ST::R>(p, c->step);
+    int zc, n_tiles;
+    unsigned grid;
+    march_grid(p, BX, TY, zc, n_tiles, grid);
+    const size_t lds = sweep_lds(c, zmarch::lds_bytes<BX, TY, T>());
+    if (p.bounce == LBM_FULLWAY)
+      hipLaunchKernelGGL((k_aa_aos_odd<ST, LBM_FULLWAY, BX, TY>), dim3(grid), dim3(BX * TY), lds,
+                         c->stream, (T*)buf, c->b.mask, c->b.links, p.nx, p.ny, p.nz, zc, n_tiles, k);
+    else
+      hipLaunchKernelGGL((k_aa_aos_odd<ST, LBM_HALFWAY, BX, TY>), dim3(grid), dim3(BX * TY), lds,
+                         c->stream, (T*)buf, c->b.mask, c->b.links, p.nx, p.ny, p.nz, zc, n_tiles, k);
     return hipGetLastError();
   });
 }

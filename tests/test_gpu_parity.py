@@ -376,14 +376,15 @@ def test_push_random_state(L, kw):
     assert abs(st["mass"] - f0.sum()) <= 1e-13 * f0.sum()
 
 
+@pytest.mark.parametrize("prop,steps", [("push", 9), ("aa", 9), ("aa", 10)])
 @pytest.mark.parametrize("bounce", ["fullway", "halfway"])
-def test_push_aos_columns_ragged_chunks(L, bounce):
-    """The AoS push marches 32 x 8 columns through z chunks: a lattice whose
-    columns end ragged in x and y and whose 100 layers split into four
-    chunks, against the oracle."""
+def test_aos_columns_ragged_chunks(L, prop, steps, bounce):
+    """The AoS push and AA neighbour step march 32 x 8 columns through z
+    chunks: a lattice whose columns end ragged in x and y and whose 100
+    layers split into four chunks, against the oracle."""
     mask = I.random_solid_mask(45, 21, 100, seed=16, fraction=0.2)
     f0 = random_state(mask, seed=17, amplitude=0.02, bounce=bounce)
-    got, ref, _ = _case(mask, 9, L, f0=f0, propagation="push", layout="aos", bounce=bounce,
+    got, ref, _ = _case(mask, steps, L, f0=f0, propagation=prop, layout="aos", bounce=bounce,
                         g=(1e-4, 3e-5, -2e-5), tau_plus=0.9)
     assert rel_maxabs(got, ref) <= TOL
 
