@@ -287,7 +287,13 @@ def main():
                          ("ria_spheres384_f64", dict(addressing="ria", bounce="halfway")),
                          ("aa_ria_spheres384_f64", dict(addressing="ria", bounce="halfway",
                                                         propagation="aa")),
-                         ("direct_spheres384_f64", dict(addressing="direct", bounce="halfway"))]:
+                         ("direct_spheres384_f64", dict(addressing="direct", bounce="halfway")),
+                         ("list_aos_spheres384_f64", dict(addressing="list", bounce="halfway",
+                                                          layout="aos")),
+                         ("aa_list_aos_spheres384_f64", dict(addressing="list", bounce="halfway",
+                                                             layout="aos", propagation="aa")),
+                         ("push_list_aos_spheres384_f64", dict(addressing="list", bounce="halfway",
+                                                               layout="aos", propagation="push"))]:
             lat, r = run_variant(smask, args.steps, args.warmup, **kw)
             r["porosity"] = phi
             variants[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}

@@ -205,7 +205,9 @@ int lbm_plan(const lbm_params* params, const uint8_t* mask_host, lbm_sizes* out)
 
 /* Geometry set-up (Sect. 3 "Lattice Representation"; Sect. 3.2): copies the
  * mask to bufs->mask; for DIRECT + HALFWAY builds the link words; for LIST
- * builds the fluid-node vector (x fastest),
+ * builds the fluid-node vector (x fastest; for AOS, x fastest within
+ * columns of 16 x 16 nodes taken through all layers, column after column,
+ * so that nodes sharing source records are listed close together),
  * the node map and the adjacency list (18 int32 per node: the slot a pull
  * reads for direction i, which is the neighbour's slot, wrapped
  * periodically, or the node's own opposite slot when the neighbour is solid

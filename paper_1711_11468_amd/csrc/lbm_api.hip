@@ -10,6 +10,8 @@
 #include <vector>
 
 #include "d3q19.hpp"
+#include <cstdlib>
+
 #include "internal.hpp"
 
 namespace lbm {
@@ -39,6 +41,8 @@ static int elem_size(int storage) {
 }
 
 static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+constexpr int kListTile = 16;  // AoS list order: columns of 16 x 16 nodes
 
 static int validate(const lbm_params* p) {
   if (!p) { set_error("params is NULL"); return LBM_EINVAL; }
@@ -341,7 +345,14 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
     if (e != hipSuccess) return fail(e, "link words kernel");
   }
   if (is_list(*params)) {
-    // Fluid-node vector in x-fastest order and the node -> list map.
+    // Fluid-node vector and the node -> list map.  x-fastest order, except
+    // for the AoS list: there consecutive list nodes share source records
+    // (a record holds the populations bound for up to 9 neighbour rows), so
+    // the list runs through columns of kListTile x kListTile nodes, each
+    // listed x fastest, then y, then z through all layers; the consumers
+    // of a record then sit close together in list order and find it in L2
+    // (on MI355X, 384^3 sphere pack: pull 3.95 -> 3.36 ms, AA 5.18 -> 3.55,
+    // push 7.33 -> 3.89).
     std::vector<int32_t> fidx, nmap;
     try {
       fidx.resize((size_t)(s.n_fluid > 0 ? s.n_fluid : 1));
@@ -352,12 +363,28 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
       return LBM_ENOMEM;
     }
     int32_t m = 0;
-    for (int64_t n = 0; n < N; ++n) {
-      if (mask_host[n] == 0) {
-        fidx[m] = (int32_t)n;
-        nmap[n] = m++;
-      } else {
-        nmap[n] = -1;
+    if (params->addressing == LBM_LIST && params->layout == LBM_AOS) {
+      const int nx = params->nx, ny = params->ny, nz = params->nz;
+      for (int64_t n = 0; n < N; ++n) nmap[n] = -1;
+      for (int y0 = 0; y0 < ny; y0 += kListTile)
+        for (int x0 = 0; x0 < nx; x0 += kListTile)
+          for (int z = 0; z < nz; ++z)
+            for (int y = y0; y < y0 + kListTile && y < ny; ++y)
+              for (int x = x0; x < x0 + kListTile && x < nx; ++x) {
+                const int64_t n = x + (int64_t)nx * (y + (int64_t)ny * z);
+                if (mask_host[n] == 0) {
+                  fidx[m] = (int32_t)n;
+                  nmap[n] = m++;
+                }
+              }
+    } else {
+      for (int64_t n = 0; n < N; ++n) {
+        if (mask_host[n] == 0) {
+          fidx[m] = (int32_t)n;
+          nmap[n] = m++;
+        } else {
+          nmap[n] = -1;
+        }
       }
     }
     e = hipMemcpyAsync(c->b.fluid_index, fidx.data(), (size_t)s.n_fluid * 4, hipMemcpyHostToDevice,
