@@ -45,16 +45,10 @@ __host__ __device__ constexpr int count_of(int c) {
   for (int i = 0; i < Q; ++i) n += Vel::cz[i] + 1 == c ? 1 : 0;
   return n;
 }
-// The directions of class c packed 5 bits each (for a runtime d), and
-// their opposites.
+// The directions of class c packed 5 bits each (for a runtime d).
 __host__ __device__ constexpr uint64_t packed_dirs(int c) {
   uint64_t v = 0;
   for (int d = 0; d < count_of(c); ++d) v |= (uint64_t)dir_of(c, d) << (5 * d);
-  return v;
-}
-__host__ __device__ constexpr uint64_t packed_opp_dirs(int c) {
-  uint64_t v = 0;
-  for (int d = 0; d < count_of(c); ++d) v |= (uint64_t)Vel::opp[dir_of(c, d)] << (5 * d);
   return v;
 }
 __host__ __device__ constexpr int idx_of(int i) {
@@ -82,20 +76,11 @@ constexpr size_t lds_bytes() {
 
 }  // namespace zmarch
 
-// The march shared by the one-step pull (AA = false: read src, store whole
-// records into dst) and the AA neighbour step (AA = true: src == dst, the
-// lattice updated in place).  In the AA neighbour step node x reads slot
-// opp(i) of x - c_i and writes f*_i into slot i of x + c_i: the staged
-// slot of direction number d of a class is then opp(dir_of(c, d)), the
-// gather is the pull's, and the results go to the neighbours' slots one by
-// one (every slot is read and then written by the one node that owns it,
-// so staging whole records in place is safe: the slots of other nodes that
-// come along are never used).
-template <class ST, int BB, int BX, int TY, bool AA>
-__device__ __forceinline__ void aos_march(const typename ST::T* src, typename ST::T* dst,
-                                          const uint8_t* mask, const uint32_t* links, int nx,
-                                          int ny, int nz, int zc, int n_tiles,
-                                          const Collide<typename ST::R>& k) {
+template <class ST, int BB, int BX, int TY>
+__global__ void __launch_bounds__(BX * TY)
+k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
+            const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx, int ny,
+            int nz, int zc, int n_tiles, Collide<typename ST::R> k) {
   using T = typename ST::T;
   using R = typename ST::R;
   using S = zmarch::Shape<BX, TY>;
@@ -134,7 +119,7 @@ __device__ __forceinline__ void aos_march(const typename ST::T* src, typename ST
     int ys = y0 - 1 + (hy < segy + 1 ? hy : segy + 1);
     xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
     ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-    const int i = (int)(((AA ? zmarch::packed_opp_dirs(c) : zmarch::packed_dirs(c)) >> (5 * d)) & 31);
+    const int i = (int)((zmarch::packed_dirs(c) >> (5 * d)) & 31);
     goff[j] = (uint32_t)((ys * nx + xs) * Q + i);
   };
 #pragma unroll
@@ -201,33 +186,7 @@ __device__ __forceinline__ void aos_march(const typename ST::T* src, typename ST
     put_level();
     put_up(s & 1);
     if (z + 1 < ze) load_layer(z + 2);
-    if (AA) {
-      // solid nodes hold no state the AA steps move (full-way reversal maps
-      // each slot onto itself)
-      if (active && !solid) {
-        if (BB == LBM_HALFWAY && (lk >> 1)) {
-#pragma unroll
-          for (int i = 1; i < Q; ++i)
-            if ((lk >> i) & 1u) f[i] = ST::load(src[n * Q + i], k.inv_scale);
-        }
-        trt_collide<R, ST::kShifted>(f, k);
-        const int x = x0 + tx, y = y0 + ty;
-        const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-        const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-        const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
-        SrStream rs((uint32_t)n, k.step, ST::kStochastic);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          const int ux = Vel::cx[i] == 1 ? xp : (Vel::cx[i] == -1 ? xm : x);
-          const int uy = Vel::cy[i] == 1 ? yp : (Vel::cy[i] == -1 ? ym : y);
-          const int uz = Vel::cz[i] == 1 ? zp : (Vel::cz[i] == -1 ? zm : z);
-          int64_t at = (((int64_t)uz * ny + uy) * nx + ux) * Q + i;
-          // link bit opp(i): x + c_i is solid, the population stays home
-          if (BB == LBM_HALFWAY && i != 0 && ((lk >> Vel::opp[i]) & 1u)) at = n * Q + Vel::opp[i];
-          dst[at] = ST::store(f[i], k.scale, rs.next());
-        }
-      }
-    } else if (active) {
+    if (active) {
       if (BB == LBM_HALFWAY) {
         if (!solid && (lk >> 1)) {
 #pragma unroll
@@ -252,22 +211,6 @@ __device__ __forceinline__ void aos_march(const typename ST::T* src, typename ST
       for (int i = 0; i < Q; ++i) dst[n * Q + i] = ST::store(f[i], k.scale, rs.next());
     }
   }
-}
-
-template <class ST, int BB, int BX, int TY>
-__global__ void __launch_bounds__(BX * TY)
-k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
-            const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx, int ny,
-            int nz, int zc, int n_tiles, Collide<typename ST::R> k) {
-  aos_march<ST, BB, BX, TY, false>(src, dst, mask, links, nx, ny, nz, zc, n_tiles, k);
-}
-
-template <class ST, int BB, int BX, int TY>
-__global__ void __launch_bounds__(BX * TY)
-k_aa_aos_odd(typename ST::T* A, const uint8_t* __restrict__ mask,
-             const uint32_t* __restrict__ links, int nx, int ny, int nz, int zc, int n_tiles,
-             Collide<typename ST::R> k) {
-  aos_march<ST, BB, BX, TY, true>(A, A, mask, links, nx, ny, nz, zc, n_tiles, k);
 }
 
 // Launch grid of a z march over BX x TY columns: about 8192 workgroups
@@ -424,6 +367,137 @@ k_push_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ 
   }
 }
 
+// ---- AA neighbour step over AoS records -------------------------------------
+// Node x reads slot opp(i) of x - c_i and, after collision, writes f*_i into
+// slot i of x + c_i, in place.  The reads follow the z march of the push
+// skeleton without the collision at the source: one thread per halo'd
+// position loads that node's record and sorts its slots into the class
+// regions (the slot staged for direction i is opp(i)); interior threads
+// gather, collide and store their 19 results slot by slot into the
+// neighbours' records.  Every slot is read and then written by the one node
+// that owns it, so staging whole records in place is safe: the slots of
+// other nodes that come along are never used.
+template <class ST, int BB, int BX, int TY>
+__global__ void __launch_bounds__((PushShape<BX, TY>::NT))
+k_aa_aos_odd(typename ST::T* A, const uint8_t* __restrict__ mask,
+             const uint32_t* __restrict__ links, int nx, int ny, int nz, int zc, int n_tiles,
+             Collide<typename ST::R> k) {
+  using T = typename ST::T;
+  using R = typename ST::R;
+  using S = PushShape<BX, TY>;
+  constexpr int HX = S::HX, P = S::P;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* L = reinterpret_cast<T*>(lds_raw);
+
+  const int per = gridDim.x / 8;
+  const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tile >= n_tiles) return;
+  const int tiles_x = (nx + BX - 1) / BX, tiles_y = (ny + TY - 1) / TY;
+  const int tx_t = tile % tiles_x;
+  const int ty_t = (tile / tiles_x) % tiles_y;
+  const int zb = (tile / tiles_x / tiles_y) * zc;
+  const int ze = zb + zc < nz ? zb + zc : nz;
+  const int x0 = tx_t * BX, y0 = ty_t * TY;
+  const int seg = nx - x0 < BX ? nx - x0 : BX;
+  const int segy = ny - y0 < TY ? ny - y0 : TY;
+  const int t = threadIdx.x;
+  const bool live = t < P;
+  const int pt = live ? t : P - 1;
+  const int hy = pt / HX, hx = pt - hy * HX;
+  const bool interior = live && hx >= 1 && hx <= seg && hy >= 1 && hy <= segy;
+  int xs = x0 - 1 + (hx < seg + 1 ? hx : seg + 1);
+  int ys = y0 - 1 + (hy < segy + 1 ? hy : segy + 1);
+  xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+  ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+  const int64_t plane_nodes = (int64_t)nx * ny;
+  const int64_t col = (int64_t)ys * nx + xs;
+  auto wrapz = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+  // neighbour record offsets of an interior node (x, y), wrapped per axis
+  const int64_t ox[3] = {xs == 0 ? nx - 1 : -1, 0, xs == nx - 1 ? 1 - nx : 1};
+  const int64_t oy[3] = {(ys == 0 ? ny - 1 : -1) * (int64_t)nx, 0,
+                         (ys == ny - 1 ? 1 - ny : 1) * (int64_t)nx};
+
+  T r[Q];
+  uint32_t geo_next = 0;
+  auto load = [&](int z) {
+    const int64_t node = wrapz(z) * plane_nodes + col;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) r[i] = A[node * Q + i];
+    geo_next = BB == LBM_HALFWAY ? links[node] : (uint32_t)mask[node];
+  };
+  // class c slots of r into its region (up: set par): direction i of the
+  // class is staged as slot opp(i)
+  auto put = [&](int c, int par) {
+    if (!live) return;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (Vel::cz[i] + 1 != c) continue;
+      const int nd = zmarch::count_of(c);
+      const int base = c == 0 ? S::R0 : (c == 1 ? S::R1 : S::R2 + par * 5 * P);
+      L[base + t * nd + zmarch::idx_of(i)] = r[Vel::opp[i]];
+    }
+  };
+
+  uint32_t geo_cur = 0;
+  load(zb - 1);
+  for (int s = -2; s < ze - zb; ++s) {
+    const int z = zb + s;
+    if (s >= 0) {
+      put(0, 0);  // down slots of layer z+1
+      __syncthreads();
+      const bool solid = BB == LBM_HALFWAY ? (geo_cur & 1u) != 0 : geo_cur != 0;
+      R f[Q];
+      if (interior && !solid) {
+        const T* up = L + S::R2 + (s & 1) * 5 * P;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const int c = Vel::cz[i] + 1, nd = zmarch::count_of(c);
+          const int pos = t - Vel::cy[i] * HX - Vel::cx[i];
+          const T* reg = c == 0 ? L + S::R0 : (c == 1 ? L + S::R1 : up);
+          f[i] = ST::load(reg[pos * nd + zmarch::idx_of(i)], k.inv_scale);
+        }
+      }
+      __syncthreads();
+      // level slots of layer z+1 (used at step s+1), up slots into the set
+      // that held layer z-1 (used at step s+2); then load layer z+2
+      put(1, 0);
+      put(2, s & 1);
+      const uint32_t lk = geo_cur;
+      geo_cur = geo_next;
+      if (s + 1 < ze - zb) load(z + 2);
+      if (interior && !solid) {
+        const int64_t n = (int64_t)z * plane_nodes + col;
+        T* const home = A + n * Q;
+        if (BB == LBM_HALFWAY && (lk >> 1)) {
+#pragma unroll
+          for (int i = 1; i < Q; ++i)
+            if ((lk >> i) & 1u) f[i] = ST::load(home[i], k.inv_scale);
+        }
+        trt_collide<R, ST::kShifted>(f, k);
+        const int64_t oz[3] = {(z == 0 ? nz - 1 : -1) * plane_nodes, 0,
+                               (z == nz - 1 ? 1 - nz : 1) * plane_nodes};
+        SrStream rs((uint32_t)n, k.step, ST::kStochastic);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const T v = ST::store(f[i], k.scale, rs.next());
+          // link bit opp(i): x + c_i is solid, the population stays home
+          if (BB == LBM_HALFWAY && i != 0 && ((lk >> Vel::opp[i]) & 1u))
+            home[Vel::opp[i]] = v;
+          else
+            home[(ox[Vel::cx[i] + 1] + oy[Vel::cy[i] + 1] + oz[Vel::cz[i] + 1]) * Q + i] = v;
+        }
+      }
+    } else {
+      // s = -2: up slots of layer zb-1 (set 0); s = -1: level and up slots
+      // of layer zb (set 1)
+      if (s == -1) put(1, 0);
+      put(2, s & 1);
+      geo_cur = geo_next;
+      load(z + 2);
+    }
+  }
+}
+
 template <class ST, int BX, int TY>
 static hipError_t launch_push_aos_t(lbm_ctx* c, const void* src, void* dst) {
   using T = typename ST::T;
@@ -482,17 +556,18 @@ hipError_t launch_aa_aos_odd(lbm_ctx* c, void* buf) {
     using ST = decltype(st);
     using T = typename ST::T;
     constexpr int BX = kAosBX, TY = kAosTY;
+    using S = PushShape<BX, TY>;
     const lbm_params& p = c->p;
     const auto k = make_collide<typename ST::R>(p, c->step);
     int zc, n_tiles;
     unsigned grid;
     march_grid(p, BX, TY, zc, n_tiles, grid);
-    const size_t lds = sweep_lds(c, zmarch::lds_bytes<BX, TY, T>());
+    const size_t lds = sweep_lds(c, (size_t)S::STAGE * sizeof(T));
     if (p.bounce == LBM_FULLWAY)
-      hipLaunchKernelGGL((k_aa_aos_odd<ST, LBM_FULLWAY, BX, TY>), dim3(grid), dim3(BX * TY), lds,
+      hipLaunchKernelGGL((k_aa_aos_odd<ST, LBM_FULLWAY, BX, TY>), dim3(grid), dim3(S::NT), lds,
                          c->stream, (T*)buf, c->b.mask, c->b.links, p.nx, p.ny, p.nz, zc, n_tiles, k);
     else
-      hipLaunchKernelGGL((k_aa_aos_odd<ST, LBM_HALFWAY, BX, TY>), dim3(grid), dim3(BX * TY), lds,
+      hipLaunchKernelGGL((k_aa_aos_odd<ST, LBM_HALFWAY, BX, TY>), dim3(grid), dim3(S::NT), lds,
                          c->stream, (T*)buf, c->b.mask, c->b.links, p.nx, p.ny, p.nz, zc, n_tiles, k);
     return hipGetLastError();
   });
