@@ -1,8 +1,10 @@
-// sweep_aos.hip - the one-step pull update for the AoS layout (Sect. 3,
-// "One Step Kernels"; node records of 19 values, compared with SoA in
-// Sect. 4.2).  Records are contiguous, so a wavefront reading one direction
-// of 64 nodes would touch 64 records; the kernel instead reads each source
-// layer once, as whole records, and redistributes it through LDS.
+// sweep_aos.hip - sweeps over the AoS layout with direct addressing: the
+// one-step pull and push (Sect. 3, "One Step Kernels") and the neighbour
+// step of the AA pattern (Sect. 3, "AA Pattern Kernels"); node records of
+// 19 values, compared with SoA in Sect. 4.2.  Records are contiguous, so a
+// wavefront reading one direction of 64 nodes would touch 64 records; the
+// kernels instead read each source layer once, as whole records, and
+// redistribute it through LDS.
 //
 // A workgroup owns a column of TY x BX nodes (rows y0.., nodes x0..) and
 // marches it through the layers zb .. ze-1 of its z chunk.  Each source
@@ -25,8 +27,9 @@
 // lines (on MI355X this beat staging the records through LDS, and
 // non-temporal stores, which bypass that assembly, were 4.6x slower).
 // Columns of 32 x 8 nodes: 1.33x the algorithmic reads for the halo, 68 KB
-// of LDS in FP64, two workgroups per compute unit.  The one-step push over
-// AoS records (below) runs the same march.
+// of LDS in FP64, two workgroups per compute unit.  The push and the AA
+// neighbour step (below) run the same march with one thread per halo'd
+// position.
 #include "launch.hpp"
 
 namespace lbm {
