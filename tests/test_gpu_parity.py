@@ -140,16 +140,17 @@ def test_block_size_bitwise_and_layouts_agree(L):
         assert rel_maxabs(run(**kw), ref) <= 1e-15, kw
 
 
-@pytest.mark.parametrize("layout", ["soa", "aos"])
-def test_full_size_channel_512_sampled(L, layout):
-    """512^3 channel in the benchmark's launch configuration (both layouts
-    the benchmark times): sampled nodes (corners, walls, interior) against
-    the windowed oracle after 12 steps, and every x-slice identical
+@pytest.mark.parametrize("layout,prop", [("soa", "os"), ("aos", "os"), ("soa", "push"),
+                                         ("aos", "push"), ("soa", "aa"), ("aos", "aa")])
+def test_full_size_channel_512_sampled(L, layout, prop):
+    """512^3 channel in the benchmark's launch configuration (every 512^3
+    form the benchmark times): sampled nodes (corners, walls, interior)
+    against the windowed oracle after 12 steps, and every x-slice identical
     (x-invariance of the duct flow)."""
     n, steps = 512, 12
     mask = I.channel_mask(n, n, n)
     phys = dict(tau_plus=0.8, magic=3 / 16, g=(1e-6, 0.0, 0.0))
-    lat = L.Lattice(mask, layout=layout, **phys)
+    lat = L.Lattice(mask, layout=layout, propagation=prop, **phys)
     lat.step(steps)
     pts = [(0, 1, 1), (5, 1, 2), (511, 2, 1), (100, 255, 256), (7, 510, 510), (300, 1, 300),
            (0, 0, 0), (400, 511, 17)]
@@ -167,14 +168,25 @@ def test_full_size_channel_512_sampled(L, layout):
     assert abs(st["mass"] - n ** 3) <= 1e-12 * n ** 3
 
 
-@pytest.mark.parametrize("addressing", ["list", "ria"])
-def test_full_size_spheres_384_list_sampled(L, addressing):
-    """384^3 porous box (fluid list, plain or run-length) against the
-    windowed oracle."""
+@pytest.fixture(scope="module")
+def spheres384():
+    return I.spheres_mask(384, 384, 384, seed=0, porosity=0.4, rmin=8, rmax=16)[0]
+
+
+@pytest.mark.parametrize("addressing,layout,prop", [
+    ("list", "soa", "os"), ("list", "soa", "aa"), ("list", "soa", "push"),
+    ("ria", "soa", "os"), ("ria", "soa", "aa"),
+    ("list", "aos", "os"), ("list", "aos", "aa"), ("list", "aos", "push"),
+    ("direct", "soa", "os")])
+def test_full_size_spheres_384_list_sampled(L, spheres384, addressing, layout, prop):
+    """384^3 porous box in every form the benchmark times on it (fluid list
+    plain or run-length, SoA or AoS records, pull, AA, push; the full array
+    with link words) against the windowed oracle."""
     n, steps = 384, 8
-    mask, phi, _ = I.spheres_mask(n, n, n, seed=0, porosity=0.4, rmin=8, rmax=16)
+    mask = spheres384
     phys = dict(tau_plus=0.8, magic=3 / 16, g=(1e-6, 0.0, 0.0))
-    lat = L.Lattice(mask, addressing=addressing, bounce="halfway", **phys)
+    lat = L.Lattice(mask, addressing=addressing, layout=layout, propagation=prop,
+                    bounce="halfway", **phys)
     lat.step(steps)
     rng = np.random.default_rng(7)
     fluid = np.flatnonzero(mask.reshape(-1) == 0)
