@@ -216,23 +216,6 @@ k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__
   }
 }
 
-// Launch grid of a z march over BX x TY columns: about 8192 workgroups
-// (16 rounds of two per compute unit measured better than fewer, longer
-// marches), z chunks of at least 32 layers (each chunk reads two extra
-// layers) split evenly, the grid padded to whole rounds of the 8 XCDs.
-static void march_grid(const lbm_params& p, int BX, int TY, int& zc, int& n_tiles,
-                       unsigned& grid) {
-  const int64_t cols = (int64_t)((p.nx + BX - 1) / BX) * ((p.ny + TY - 1) / TY);
-  int64_t nzc = (8192 + cols - 1) / cols;
-  const int64_t max_chunks = (p.nz + 31) / 32;
-  if (nzc > max_chunks) nzc = max_chunks;
-  if (nzc < 1) nzc = 1;
-  zc = (int)((p.nz + nzc - 1) / nzc);
-  nzc = (p.nz + zc - 1) / zc;
-  n_tiles = (int)(cols * nzc);
-  grid = (unsigned)((n_tiles + 7) / 8 * 8);
-}
-
 // ---- one-step push over AoS records ---------------------------------------
 // The push writes f*_i(x) into slot i of x + c_i (or, under half-way
 // bounce-back towards a solid node, into slot opp(i) of x).  Seen from the
