@@ -236,6 +236,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cnn-only", choices=["infer_128", "train_64x4", "both"], default=None,
                     help="time only the warm-start network (for kernel traces)")
+    ap.add_argument("--variants", default=None,
+                    help="comma-separated variant names to run after the headline "
+                         "(for counter runs); skips the warm-start and network sections")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; the multi-GPU path is not implemented "
@@ -263,6 +266,8 @@ def main():
     torch.cuda.empty_cache()
 
     variants = {}
+    only = set(args.variants.split(",")) if args.variants else None
+    wanted = lambda name: only is None or name in only  # noqa: E731
     if not args.headline_only:
         for name, kw in [("aos_f64", dict(layout="aos")),
                          ("soa_f32_shifted", dict(storage="f32s")),
@@ -272,36 +277,42 @@ def main():
                          ("aa_soa_f64", dict(propagation="aa")),
                          ("push_soa_f64", dict(propagation="push")),
                          ("push_aos_f64", dict(propagation="push", layout="aos"))]:
+            if not wanted(name):
+                continue
             log("variant %s" % name)
             lat, r = run_variant(mask, args.steps, args.warmup, **kw)
             variants[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
             del lat
             torch.cuda.empty_cache()
-        log("variant list 384^3 spheres")
-        smask, phi, _ = I.spheres_mask(384, 384, 384, seed=0, porosity=0.4, rmin=8, rmax=16)
-        for name, kw in [("list_spheres384_f64", dict(addressing="list", bounce="halfway")),
-                         ("aa_list_spheres384_f64", dict(addressing="list", bounce="halfway",
-                                                         propagation="aa")),
-                         ("push_list_spheres384_f64", dict(addressing="list", bounce="halfway",
-                                                           propagation="push")),
-                         ("ria_spheres384_f64", dict(addressing="ria", bounce="halfway")),
-                         ("aa_ria_spheres384_f64", dict(addressing="ria", bounce="halfway",
-                                                        propagation="aa")),
-                         ("direct_spheres384_f64", dict(addressing="direct", bounce="halfway")),
-                         ("list_aos_spheres384_f64", dict(addressing="list", bounce="halfway",
-                                                          layout="aos")),
-                         ("aa_list_aos_spheres384_f64", dict(addressing="list", bounce="halfway",
-                                                             layout="aos", propagation="aa")),
-                         ("push_list_aos_spheres384_f64", dict(addressing="list", bounce="halfway",
-                                                               layout="aos", propagation="push"))]:
+        spheres = [("list_spheres384_f64", dict(addressing="list", bounce="halfway")),
+                   ("aa_list_spheres384_f64", dict(addressing="list", bounce="halfway",
+                                                   propagation="aa")),
+                   ("push_list_spheres384_f64", dict(addressing="list", bounce="halfway",
+                                                     propagation="push")),
+                   ("ria_spheres384_f64", dict(addressing="ria", bounce="halfway")),
+                   ("aa_ria_spheres384_f64", dict(addressing="ria", bounce="halfway",
+                                                  propagation="aa")),
+                   ("direct_spheres384_f64", dict(addressing="direct", bounce="halfway")),
+                   ("list_aos_spheres384_f64", dict(addressing="list", bounce="halfway",
+                                                    layout="aos")),
+                   ("aa_list_aos_spheres384_f64", dict(addressing="list", bounce="halfway",
+                                                       layout="aos", propagation="aa")),
+                   ("push_list_aos_spheres384_f64", dict(addressing="list", bounce="halfway",
+                                                         layout="aos", propagation="push"))]
+        spheres = [(name, kw) for name, kw in spheres if wanted(name)]
+        if spheres:
+            log("variant list 384^3 spheres")
+            smask, phi, _ = I.spheres_mask(384, 384, 384, seed=0, porosity=0.4, rmin=8, rmax=16)
+        for name, kw in spheres:
             lat, r = run_variant(smask, args.steps, args.warmup, **kw)
             r["porosity"] = phi
             variants[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
             del lat
             torch.cuda.empty_cache()
 
-    steady = None if args.headline_only else warm_vs_cold()
-    cnn = None if args.headline_only else cnn_throughput()
+    extras = not args.headline_only and only is None
+    steady = warm_vs_cold() if extras else None
+    cnn = cnn_throughput() if extras else None
     cpu = None if args.no_cpu else cpu_baseline()
     achieved = head["achieved_gbs"]
     traffic = measured_traffic() if n == 512 else None

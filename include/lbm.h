@@ -149,8 +149,8 @@ typedef struct {
   int64_t node_map_bytes;   /* LIST, LIST_RIA: N int32 (node -> list/-1)   */
   int64_t links_bytes;      /* DIRECT + HALFWAY: N uint32 link words       */
   int64_t u_prev_bytes;     /* 3*n_sites doubles for the residual          */
-  int64_t scratch_bytes;    /* reduction partials (for OS + SOA + DIRECT
-                               one record per (y, z) row, at least 4096)   */
+  int64_t scratch_bytes;    /* reduction partials (for OS + DIRECT one
+                               record per workgroup of the fused sweep)    */
   double bytes_per_update;  /* algorithmic HBM bytes per site update       */
   int64_t n_runs;           /* LIST_RIA: number of runs; else 0            */
   int64_t ria_bytes;        /* LIST_RIA: run tables (library-internal
@@ -262,12 +262,12 @@ int lbm_macroscopic(lbm_ctx* ctx, double* rho_dev, double* u_dev,
  * *out that lbm_macroscopic(ctx, NULL, NULL, out) returns before the update
  * (out->step is the count before it, and the residual history advances
  * likewise), followed by the same update as lbm_step(ctx, 1).  For
- * LBM_OS + LBM_SOA + LBM_DIRECT the moments are taken inside the sweep from
- * the populations it gathers (one pass over the lattice instead of two, the
- * diagnostics are part of the fused kernel, Sect. 3 "One Step Kernels");
- * every other form runs the two calls in turn.  Sums are FP64 and combine
- * per-row partials in a fixed order (not the order lbm_macroscopic uses, so
- * sums can differ from it in the last bits).  The update is applied whatever
+ * LBM_OS + LBM_DIRECT (SoA or AoS) the moments are taken inside the sweep
+ * from the populations it gathers (one pass over the lattice instead of
+ * two, the diagnostics are part of the fused kernel, Sect. 3 "One Step
+ * Kernels"); every other form runs the two calls in turn.  Sums are FP64
+ * and combine per-workgroup partials in a fixed order (not the order
+ * lbm_macroscopic uses, so sums can differ from it in the last bits).  The update is applied whatever
  * the state holds.  Synchronises.  Returns ENONFINITE if the state it
  * started from had a non-finite fluid population (the stats are filled and
  * the update has run).  Errors: EINVAL, EDEVICE, ENONFINITE. */

@@ -47,6 +47,12 @@ inline void* pdf_buf(lbm_ctx* c, int which) { return which == 0 ? c->b.pdf_a : c
 // buf, the kernel chosen by c->aa_odd).
 hipError_t launch_pull(lbm_ctx* c, const void* src, void* dst);
 hipError_t launch_pull_aos(lbm_ctx* c, const void* src, void* dst);
+// The AoS pull with the diagnostics fused in: one partial record per column
+// into `partials`; *records = number written.
+hipError_t launch_pull_aos_diag(lbm_ctx* c, const void* src, void* dst, int residual_mode,
+                                double* partials, int64_t* records);
+// Column shape of the AoS marches (x, y nodes).
+constexpr int kAosBX = 32, kAosTY = 8;
 hipError_t launch_push_aos(lbm_ctx* c, const void* src, void* dst);
 hipError_t launch_aa_aos_odd(lbm_ctx* c, void* buf);
 hipError_t launch_push(lbm_ctx* c, const void* src, void* dst);
@@ -85,14 +91,20 @@ hipError_t launch_final_reduce(lbm_ctx* c, double* partials, int64_t n_blocks, i
 hipError_t launch_reduce_records(lbm_ctx* c, double* partials, int64_t n, int n_slots,
                                  uint32_t max_mask, double* stage, double* out_dev);
 constexpr int64_t kMaxReduceRecords = 4096;
-// Forms whose sweep can carry the diagnostics (one record per (y, z) row).
+// Forms whose sweep can carry the diagnostics: the one-step pull with
+// direct addressing (SoA: one record per (y, z) row; AoS: one per column of
+// the z march).
 inline bool fused_diag_form(const lbm_params& p) {
-  return p.propagation == LBM_OS && p.layout == LBM_SOA && p.addressing == LBM_DIRECT;
+  return p.propagation == LBM_OS && p.addressing == LBM_DIRECT;
 }
 // Scratch layout: [records][kStatSlots] partials, [kMaxReduceRecords]
-// [kStatSlots] second-stage partials, [kStatSlots] result.
+// [kStatSlots] second-stage partials, [kStatSlots] result.  The AoS march
+// runs at most 8192 + (its columns per layer) workgroups.
 inline int64_t stat_records(const lbm_params& p) {
-  const int64_t rows = fused_diag_form(p) ? (int64_t)p.ny * p.nz : 0;
+  int64_t rows = 0;
+  if (fused_diag_form(p))
+    rows = p.layout == LBM_SOA ? (int64_t)p.ny * p.nz
+                               : 8192 + (int64_t)((p.nx + kAosBX - 1) / kAosBX) * ((p.ny + kAosTY - 1) / kAosTY);
   return rows > kMaxReduceRecords ? rows : kMaxReduceRecords;
 }
 // Slot layouts of the two reductions.

@@ -544,9 +544,14 @@ int lbm_step_diag(lbm_ctx* c, lbm_stats* out) {
   const int residual_mode = c->b.u_prev ? (c->u_prev_valid ? 2 : 1) : 0;
   double* partials = (double*)c->b.scratch;
   int64_t rows = 0;
-  LBM_HIP(launch_pull_diag(c, pdf_buf(c, c->cur), pdf_buf(c, 1 - c->cur), residual_mode, partials,
-                           &rows),
-          "fused sweep launch");
+  if (c->p.layout == LBM_SOA)
+    LBM_HIP(launch_pull_diag(c, pdf_buf(c, c->cur), pdf_buf(c, 1 - c->cur), residual_mode,
+                             partials, &rows),
+            "fused sweep launch");
+  else
+    LBM_HIP(launch_pull_aos_diag(c, pdf_buf(c, c->cur), pdf_buf(c, 1 - c->cur), residual_mode,
+                                 partials, &rows),
+            "fused sweep launch");
   const int64_t described = c->step;
   c->cur = 1 - c->cur;
   c->step += 1;

@@ -30,6 +30,7 @@
 // of LDS in FP64, two workgroups per compute unit.  The push and the AA
 // neighbour step (below) run the same march with one thread per halo'd
 // position.
+#include "diag.hpp"
 #include "launch.hpp"
 
 namespace lbm {
@@ -79,11 +80,17 @@ constexpr size_t lds_bytes() {
 
 }  // namespace zmarch
 
-template <class ST, int BB, int BX, int TY>
-__global__ void __launch_bounds__(BX * TY)
-k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
-            const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx, int ny,
-            int nz, int zc, int n_tiles, Collide<typename ST::R> k) {
+// The pull march; with DIAG the diagnostics of the state it reads (the
+// gathered populations, after the half-way substitution) are accumulated
+// per thread and reduced into one partial record per column.
+template <class ST, int BB, int BX, int TY, bool DIAG>
+__device__ __forceinline__ void aos_pull_march(const typename ST::T* __restrict__ src,
+                                               typename ST::T* __restrict__ dst,
+                                               const uint8_t* __restrict__ mask,
+                                               const uint32_t* __restrict__ links, int nx, int ny,
+                                               int nz, int zc, int n_tiles,
+                                               const Collide<typename ST::R>& k,
+                                               const DiagArgs& dg) {
   using T = typename ST::T;
   using R = typename ST::R;
   using S = zmarch::Shape<BX, TY>;
@@ -148,6 +155,11 @@ k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__
     for (int j = 0; j < K1; ++j) Lt[S::D1 + j * NT] = r[K0 + j];
   };
 
+  double acc[M_COUNT];
+#pragma unroll
+  for (int q = 0; q < M_COUNT; ++q) acc[q] = 0.0;
+  const int64_t n_all = (int64_t)nx * ny * nz;
+
   // prologue: up populations of layer zb-1 (set 0), level and up of zb (set 1)
   load_layer(zb - 1);
   put_up(0);
@@ -197,6 +209,10 @@ k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__
             if ((lk >> i) & 1u) f[i] = ST::load(src[n * Q + Vel::opp[i]], k.inv_scale);
         }
       }
+      // half-way solids hold no state; full-way solids hold populations in transit
+      if constexpr (DIAG) {
+        if (!(BB == LBM_HALFWAY && solid)) diag_node<ST>(f, !solid, n, n_all, dg, acc);
+      }
       if (!solid) {
         trt_collide<R, ST::kShifted>(f, k);
       } else if (BB == LBM_FULLWAY) {
@@ -214,6 +230,30 @@ k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__
       for (int i = 0; i < Q; ++i) dst[n * Q + i] = ST::store(f[i], k.scale, rs.next());
     }
   }
+  if constexpr (DIAG) {
+    block_reduce<M_COUNT>(acc, 1u << M_UMAX);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int q = 0; q < M_COUNT; ++q) dg.partials[(int64_t)tile * kStatSlots + q] = acc[q];
+    }
+  }
+}
+
+template <class ST, int BB, int BX, int TY>
+__global__ void __launch_bounds__(BX * TY)
+k_sweep_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
+            const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx, int ny,
+            int nz, int zc, int n_tiles, Collide<typename ST::R> k) {
+  aos_pull_march<ST, BB, BX, TY, false>(src, dst, mask, links, nx, ny, nz, zc, n_tiles, k,
+                                        DiagArgs{});
+}
+
+template <class ST, int BB, int BX, int TY>
+__global__ void __launch_bounds__(BX * TY)
+k_sweep_aos_diag(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
+                 const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx,
+                 int ny, int nz, int zc, int n_tiles, Collide<typename ST::R> k, DiagArgs d) {
+  aos_pull_march<ST, BB, BX, TY, true>(src, dst, mask, links, nx, ny, nz, zc, n_tiles, k, d);
 }
 
 // ---- one-step push over AoS records ---------------------------------------
@@ -512,7 +552,6 @@ hipError_t launch_push_aos(lbm_ctx* c, const void* src, void* dst) {
   });
 }
 
-constexpr int kAosBX = 32, kAosTY = 8;
 
 hipError_t launch_pull_aos(lbm_ctx* c, const void* src, void* dst) {
   return with_storage(c->p, [&](auto st) -> hipError_t {
@@ -533,6 +572,38 @@ hipError_t launch_pull_aos(lbm_ctx* c, const void* src, void* dst) {
       hipLaunchKernelGGL((k_sweep_aos<ST, LBM_HALFWAY, BX, TY>), dim3(grid), dim3(BX * TY), lds,
                          c->stream, (const T*)src, (T*)dst, c->b.mask, c->b.links, p.nx, p.ny,
                          p.nz, zc, n_tiles, k);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_pull_aos_diag(lbm_ctx* c, const void* src, void* dst, int residual_mode,
+                                double* partials, int64_t* records) {
+  return with_storage(c->p, [&](auto st) -> hipError_t {
+    using ST = decltype(st);
+    using T = typename ST::T;
+    constexpr int BX = kAosBX, TY = kAosTY;
+    const lbm_params& p = c->p;
+    const auto k = make_collide<typename ST::R>(p, c->step);
+    int zc, n_tiles;
+    unsigned grid;
+    march_grid(p, BX, TY, zc, n_tiles, grid);
+    *records = n_tiles;
+    DiagArgs d;
+    d.gx = p.g[0];
+    d.gy = p.g[1];
+    d.gz = p.g[2];
+    d.u_prev = c->b.u_prev;
+    d.residual_mode = residual_mode;
+    d.partials = partials;
+    const size_t lds = sweep_lds(c, zmarch::lds_bytes<BX, TY, T>());
+    if (p.bounce == LBM_FULLWAY)
+      hipLaunchKernelGGL((k_sweep_aos_diag<ST, LBM_FULLWAY, BX, TY>), dim3(grid), dim3(BX * TY),
+                         lds, c->stream, (const T*)src, (T*)dst, c->b.mask, c->b.links, p.nx, p.ny,
+                         p.nz, zc, n_tiles, k, d);
+    else
+      hipLaunchKernelGGL((k_sweep_aos_diag<ST, LBM_HALFWAY, BX, TY>), dim3(grid), dim3(BX * TY),
+                         lds, c->stream, (const T*)src, (T*)dst, c->b.mask, c->b.links, p.nx, p.ny,
+                         p.nz, zc, n_tiles, k, d);
     return hipGetLastError();
   });
 }

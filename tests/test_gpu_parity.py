@@ -166,6 +166,14 @@ def test_full_size_channel_512_sampled(L, layout, prop):
     st = lat.macroscopic()
     # mass over all nodes (walls hold populations in transit) is conserved
     assert abs(st["mass"] - n ** 3) <= 1e-12 * n ** 3
+    if prop == "os":
+        # the fused sweep + diagnostics on the same state: the same stats
+        # (its records exceed one reduction stage) and a zero residual
+        sd = lat.step_diag()
+        assert sd["step"] == st["step"] and sd["residual"] == 0.0
+        assert abs(sd["mass"] - st["mass"]) <= 1e-13 * st["mass"]
+        assert sd["u_max"] == st["u_max"]
+        np.testing.assert_allclose(sd["momentum"], st["momentum"], rtol=1e-12, atol=1e-9)
 
 
 @pytest.fixture(scope="module")
