@@ -431,23 +431,26 @@ __global__ void k_lrelu_bwd(const float* __restrict__ dx, const uint16_t* __rest
   d[i] = f2bf(bf2f(y[i]) > 0.f ? dx[i] : dx[i] * slope);
 }
 
+// Index arithmetic of the element-wise kernels below runs in I: 32-bit when
+// the element count allows it (64-bit division is a long instruction
+// sequence on the GPU and dominated these memory-bound kernels).
+template <typename I>
 __global__ void k_up_concat(const uint16_t* __restrict__ coarse, const uint16_t* __restrict__ skip,
-                            uint16_t* __restrict__ cat, int64_t nvox, int d, int h, int w, int c1,
-                            int c2) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int ct = c1 + c2;
+                            uint16_t* __restrict__ cat, I nvox, I d, I h, I w, I c1, I c2) {
+  const I e = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+  const I ct = c1 + c2;
   if (e >= nvox * ct) return;
-  const int64_t v = e / ct;
-  const int c = (int)(e - v * ct);
+  const I v = e / ct;
+  const I c = e - v * ct;
   if (c < c1) {
-    int64_t t = v;
-    const int xx = (int)(t % w);
+    I t = v;
+    const I xx = t % w;
     t /= w;
-    const int yy = (int)(t % h);
+    const I yy = t % h;
     t /= h;
-    const int zz = (int)(t % d);
-    const int b = (int)(t / d);
-    const int64_t cv = (((int64_t)b * (d / 2) + zz / 2) * (h / 2) + yy / 2) * (w / 2) + xx / 2;
+    const I zz = t % d;
+    const I b = t / d;
+    const I cv = ((b * (d / 2) + zz / 2) * (h / 2) + yy / 2) * (w / 2) + xx / 2;
     cat[e] = coarse[cv * c1 + c];
   } else {
     cat[e] = skip[v * c2 + (c - c1)];
@@ -456,24 +459,24 @@ __global__ void k_up_concat(const uint16_t* __restrict__ coarse, const uint16_t*
 
 // The same with 8 channels (16 bytes) per thread, for channel counts that
 // are multiples of 8.
+template <typename I>
 __global__ void k_up_concat8(const uint16_t* __restrict__ coarse, const uint16_t* __restrict__ skip,
-                             uint16_t* __restrict__ cat, int64_t nvox, int d, int h, int w, int c1,
-                             int c2) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int g1 = c1 / 8, gt = (c1 + c2) / 8;
+                             uint16_t* __restrict__ cat, I nvox, I d, I h, I w, I c1, I c2) {
+  const I e = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+  const I g1 = c1 / 8, gt = (c1 + c2) / 8;
   if (e >= nvox * gt) return;
-  const int64_t v = e / gt;
-  const int gi = (int)(e - v * gt);
+  const I v = e / gt;
+  const I gi = e - v * gt;
   uint4 val;
   if (gi < g1) {
-    int64_t t = v;
-    const int xx = (int)(t % w);
+    I t = v;
+    const I xx = t % w;
     t /= w;
-    const int yy = (int)(t % h);
+    const I yy = t % h;
     t /= h;
-    const int zz = (int)(t % d);
-    const int b = (int)(t / d);
-    const int64_t cv = (((int64_t)b * (d / 2) + zz / 2) * (h / 2) + yy / 2) * (w / 2) + xx / 2;
+    const I zz = t % d;
+    const I b = t / d;
+    const I cv = ((b * (d / 2) + zz / 2) * (h / 2) + yy / 2) * (w / 2) + xx / 2;
     val = *(const uint4*)(coarse + cv * c1 + gi * 8);
   } else {
     val = *(const uint4*)(skip + v * c2 + (gi - g1) * 8);
@@ -481,35 +484,37 @@ __global__ void k_up_concat8(const uint16_t* __restrict__ coarse, const uint16_t
   *(uint4*)(cat + v * (c1 + c2) + gi * 8) = val;
 }
 
+template <typename I>
 __global__ void k_split_down_coarse(const float* __restrict__ dcat, float* __restrict__ dcoarse,
-                                    int64_t ncoarse, int d, int h, int w, int c1, int c2) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                    I ncoarse, I d, I h, I w, I c1, I c2) {
+  const I e = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
   if (e >= ncoarse * c1) return;
-  const int64_t v = e / c1;
-  const int c = (int)(e - v * c1);
-  const int dc = d / 2, hc = h / 2, wc = w / 2;
-  int64_t t = v;
-  const int xc = (int)(t % wc);
+  const I v = e / c1;
+  const I c = e - v * c1;
+  const I dc = d / 2, hc = h / 2, wc = w / 2;
+  I t = v;
+  const I xc = t % wc;
   t /= wc;
-  const int yc = (int)(t % hc);
+  const I yc = t % hc;
   t /= hc;
-  const int zc = (int)(t % dc);
-  const int b = (int)(t / dc);
+  const I zc = t % dc;
+  const I b = t / dc;
   float s = 0.f;
   for (int k = 0; k < 8; ++k) {
-    const int zz = 2 * zc + (k >> 2), yy = 2 * yc + ((k >> 1) & 1), xx = 2 * xc + (k & 1);
-    const int64_t fv = (((int64_t)b * d + zz) * h + yy) * w + xx;
+    const I zz = 2 * zc + (k >> 2), yy = 2 * yc + ((k >> 1) & 1), xx = 2 * xc + (k & 1);
+    const I fv = ((b * d + zz) * h + yy) * w + xx;
     s += dcat[fv * (c1 + c2) + c];
   }
   dcoarse[e] = s;
 }
 
+template <typename I>
 __global__ void k_split_down_skip(const float* __restrict__ dcat, float* __restrict__ dskip,
-                                  int64_t nfine, int c1, int c2) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                  I nfine, I c1, I c2) {
+  const I e = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
   if (e >= nfine * c2) return;
-  const int64_t v = e / c2;
-  const int c = (int)(e - v * c2);
+  const I v = e / c2;
+  const I c = e - v * c2;
   dskip[e] = dcat[v * (c1 + c2) + c1 + c];
 }
 
@@ -602,12 +607,13 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ gr, floa
   pb[i] = f2bf(pi);
 }
 
-__global__ void k_prepare_input(const uint8_t* __restrict__ mask, uint16_t* __restrict__ x,
-                                int64_t n, int cpad) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <typename I>
+__global__ void k_prepare_input(const uint8_t* __restrict__ mask, uint16_t* __restrict__ x, I n,
+                                I cpad) {
+  const I e = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
   if (e >= n * cpad) return;
-  const int64_t i = e / cpad;
-  const int c = (int)(e - i * cpad);
+  const I i = e / cpad;
+  const I c = e - i * cpad;
   const bool solid = mask[i] != 0;
   float v = 0.f;
   if (c == 0) v = solid ? 1.f : 0.f;
@@ -902,12 +908,24 @@ int nn_up_concat(const uint16_t* coarse, const uint16_t* skip, uint16_t* cat, in
     return -1;
   }
   const int64_t nvox = (int64_t)batch * d * h * w;
-  if (c1 % 8 == 0 && c2 % 8 == 0)
-    hipLaunchKernelGGL(k_up_concat8, dim3(nblk(nvox * ((c1 + c2) / 8), 256)), dim3(256), 0,
-                       (hipStream_t)stream, coarse, skip, cat, nvox, d, h, w, c1, c2);
-  else
-    hipLaunchKernelGGL(k_up_concat, dim3(nblk(nvox * (c1 + c2), 256)), dim3(256), 0,
-                       (hipStream_t)stream, coarse, skip, cat, nvox, d, h, w, c1, c2);
+  const bool small = nvox * (c1 + c2) < ((int64_t)1 << 31);
+  if (c1 % 8 == 0 && c2 % 8 == 0) {
+    const dim3 grid(nblk(nvox * ((c1 + c2) / 8), 256));
+    if (small)
+      hipLaunchKernelGGL(k_up_concat8<uint32_t>, grid, dim3(256), 0, (hipStream_t)stream, coarse,
+                         skip, cat, (uint32_t)nvox, d, h, w, c1, c2);
+    else
+      hipLaunchKernelGGL(k_up_concat8<int64_t>, grid, dim3(256), 0, (hipStream_t)stream, coarse,
+                         skip, cat, nvox, d, h, w, c1, c2);
+  } else {
+    const dim3 grid(nblk(nvox * (c1 + c2), 256));
+    if (small)
+      hipLaunchKernelGGL(k_up_concat<uint32_t>, grid, dim3(256), 0, (hipStream_t)stream, coarse,
+                         skip, cat, (uint32_t)nvox, d, h, w, c1, c2);
+    else
+      hipLaunchKernelGGL(k_up_concat<int64_t>, grid, dim3(256), 0, (hipStream_t)stream, coarse,
+                         skip, cat, nvox, d, h, w, c1, c2);
+  }
   NN_HIP_CHECK("up concat");
   return 0;
 }
@@ -920,10 +938,18 @@ int nn_split_down(const float* dcat, float* dcoarse, float* dskip, int32_t batch
   }
   const int64_t nfine = (int64_t)batch * d * h * w;
   const int64_t ncoarse = nfine / 8;
-  hipLaunchKernelGGL(k_split_down_coarse, dim3(nblk(ncoarse * c1, 256)), dim3(256), 0,
-                     (hipStream_t)stream, dcat, dcoarse, ncoarse, d, h, w, c1, c2);
-  hipLaunchKernelGGL(k_split_down_skip, dim3(nblk(nfine * c2, 256)), dim3(256), 0,
-                     (hipStream_t)stream, dcat, dskip, nfine, c1, c2);
+  const dim3 gc(nblk(ncoarse * c1, 256)), gs(nblk(nfine * c2, 256));
+  if (nfine * (c1 + c2) < ((int64_t)1 << 31)) {
+    hipLaunchKernelGGL(k_split_down_coarse<uint32_t>, gc, dim3(256), 0, (hipStream_t)stream, dcat,
+                       dcoarse, (uint32_t)ncoarse, d, h, w, c1, c2);
+    hipLaunchKernelGGL(k_split_down_skip<uint32_t>, gs, dim3(256), 0, (hipStream_t)stream, dcat,
+                       dskip, (uint32_t)nfine, c1, c2);
+  } else {
+    hipLaunchKernelGGL(k_split_down_coarse<int64_t>, gc, dim3(256), 0, (hipStream_t)stream, dcat,
+                       dcoarse, ncoarse, d, h, w, c1, c2);
+    hipLaunchKernelGGL(k_split_down_skip<int64_t>, gs, dim3(256), 0, (hipStream_t)stream, dcat,
+                       dskip, nfine, c1, c2);
+  }
   NN_HIP_CHECK("split down");
   return 0;
 }
@@ -962,8 +988,12 @@ int nn_adam_step(float* param, const float* grad, float* m, float* v, uint16_t* 
 
 int nn_prepare_input(const uint8_t* mask, uint16_t* x, int64_t n, int32_t c_pad, void* stream) {
   if (!mask || !x || n < 1 || c_pad < 2) { set_error("bad arguments"); return -1; }
-  hipLaunchKernelGGL(k_prepare_input, dim3(nblk(n * c_pad, 256)), dim3(256), 0,
-                     (hipStream_t)stream, mask, x, n, c_pad);
+  if ((int64_t)n * c_pad < ((int64_t)1 << 31))
+    hipLaunchKernelGGL(k_prepare_input<uint32_t>, dim3(nblk((int64_t)n * c_pad, 256)), dim3(256), 0,
+                       (hipStream_t)stream, mask, x, (uint32_t)n, (uint32_t)c_pad);
+  else
+    hipLaunchKernelGGL(k_prepare_input<int64_t>, dim3(nblk((int64_t)n * c_pad, 256)), dim3(256), 0,
+                       (hipStream_t)stream, mask, x, (int64_t)n, (int64_t)c_pad);
   NN_HIP_CHECK("prepare input");
   return 0;
 }
