@@ -80,7 +80,22 @@ __device__ __forceinline__ void axis_offsets(int c, int s, int n, int stride, in
   for (int d = -1; d <= 1; ++d) o[d + 1] = (wrapi(c0 + d, n) - c0) * stride;
 }
 
-template <int STRIDE, int TAPS, int NB, bool OUTF32, int MT>
+// Moves an A fragment one voxel along the 16 voxels (lanes) of each
+// 16-lane row of the wavefront: lane r takes lane r - 1 (down) or r + 1
+// (up); the edge lane with no neighbour in the row keeps `edge`.
+__device__ __forceinline__ s4 frag_shift(s4 edge, s4 v, bool up) {
+  union U { s4 f; int i[2]; };
+  U e, a, r;
+  e.f = edge;
+  a.f = v;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    r.i[h] = up ? __builtin_amdgcn_update_dpp(e.i[h], a.i[h], 0x101, 0xF, 0xF, false)   // row_shl:1
+                : __builtin_amdgcn_update_dpp(e.i[h], a.i[h], 0x111, 0xF, 0xF, false);  // row_shr:1
+  return r.f;
+}
+
+template <int STRIDE, int TAPS, int NB, bool OUTF32, int MT, bool XS>
 __global__ void __launch_bounds__(256)
 k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
            const float* __restrict__ bias, void* __restrict__ y, int nsplit, Geom g) {
@@ -116,8 +131,51 @@ k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f4{0.f, 0.f, 0.f, 0.f};
   const uint16_t* xl = x + 4 * kq;
+  if constexpr (XS) {
+    // Stride 1 with x-aligned tiles: the three x taps of a (z, y) pair read
+    // the same 16 voxels shifted by one, so one fragment is loaded and
+    // shifted across lanes; only the voxels just outside the tile come
+    // from memory (one lane per row).
 #pragma unroll
-  for (int tap = 0; tap < TAPS; ++tap) {
+    for (int zy = 0; zy < 9; ++zy) {
+      const int iz = zy / 3, iy = zy % 3;
+      const uint16_t *xc[MT], *xm[MT], *xq[MT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int o = ao[m].base + ao[m].oz[iz] + ao[m].oy[iy];
+        xc[m] = xl + (int64_t)(o + ao[m].ox[1]) * g.ci;
+        xm[m] = xl + (int64_t)(o + ao[m].ox[0]) * g.ci;
+        xq[m] = xl + (int64_t)(o + ao[m].ox[2]) * g.ci;
+      }
+      const uint16_t* wp = w + ((int64_t)(3 * zy) * g.co + part * NB * 16 + row) * g.ci + 4 * kq;
+      const int64_t tap_stride = (int64_t)g.co * g.ci;
+      for (int c0 = 0; c0 < g.ci; c0 += 16) {
+        s4 a[3][MT], bv[NB];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          a[1][m] = *(const s4*)(xc[m] + c0);
+          s4 e0 = a[1][m], e2 = a[1][m];
+          if (row == 0) e0 = *(const s4*)(xm[m] + c0);
+          if (row == 15) e2 = *(const s4*)(xq[m] + c0);
+          a[0][m] = frag_shift(e0, a[1][m], false);
+          a[2][m] = frag_shift(e2, a[1][m], true);
+        }
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            bv[nb] = *(const s4*)(wp + ix * tap_stride + (int64_t)nb * 16 * g.ci + c0);
+#pragma unroll
+          for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+              acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ix][m], bv[nb], acc[m][nb], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int tap = 0; tap < (XS ? 0 : TAPS); ++tap) {
     const int iz = TAPS == 27 ? tap / 9 : 1, iy = TAPS == 27 ? (tap / 3) % 3 : 1,
               ix = TAPS == 27 ? tap % 3 : 1;
     const uint16_t* xp[MT];
@@ -729,11 +787,17 @@ static void launch_fwd_mt(int nb, const uint16_t* x, const uint16_t* w, const fl
   const int nbw = nb / nsplit;
   const int64_t tiles = nblk(g.m_out / 16, MT);
   const dim3 grid(pad_xcd(nblk(tiles * nsplit, 4))), block(256);
+  // stride 1 with rows of whole tiles: the x taps share one fragment
+  const bool xs = STRIDE == 1 && TAPS == 27 && g.Wo % 16 == 0;
   switch (nbw) {
 #define CASE(N)                                                                                  \
   case N:                                                                                        \
-    hipLaunchKernelGGL((k_conv_fwd<STRIDE, TAPS, N, F32, MT>), grid, block, 0, s, x, w, bias, y,  \
-                       nsplit, g);                                                               \
+    if (xs)                                                                                      \
+      hipLaunchKernelGGL((k_conv_fwd<STRIDE, TAPS, N, F32, MT, true>), grid, block, 0, s, x, w,  \
+                         bias, y, nsplit, g);                                                    \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_conv_fwd<STRIDE, TAPS, N, F32, MT, false>), grid, block, 0, s, x, w, \
+                         bias, y, nsplit, g);                                                    \
     break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE

@@ -30,6 +30,9 @@ def rel(a, b):
 CASES = [  # (batch, n, c_in, c_out, stride, taps)
     (2, 16, 16, 16, 1, 27), (1, 8, 32, 64, 1, 27), (1, 16, 48, 16, 1, 27), (1, 8, 128, 64, 1, 27),
     (2, 16, 16, 32, 2, 27), (1, 16, 64, 64, 2, 27), (1, 16, 96, 32, 1, 27), (2, 16, 16, 16, 1, 1),
+    # grids large enough for 2 and 4 tiles per wavefront (the forward's
+    # x-shifted fragments with several tiles)
+    (2, 48, 16, 32, 1, 27), (1, 64, 16, 16, 1, 27),
 ]
 
 
