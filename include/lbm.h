@@ -120,8 +120,8 @@ typedef struct {
   int32_t block;            /* threads per workgroup, 0 = default; a
                                multiple of 64 up to 1024 (the AA kernels
                                take at most 512 and cut larger values; the
-                               AoS one-step pull and push always run their
-                               own column shapes)                          */
+                               AoS column marches - pull, push, AA
+                               neighbour step - run their own shapes)      */
   int32_t pad;              /* extra elements between direction arrays
                                (SOA/LIST); -1 = automatic                  */
   int32_t cu_slots;         /* at most this many sweep workgroups per
