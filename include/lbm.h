@@ -71,7 +71,8 @@ extern "C" {
 #define LBM_EOVERFLOW (-3)   /* lattice too large for 32-bit indices       */
 #define LBM_EDEVICE (-4)     /* a HIP call failed (see lbm_last_error)     */
 #define LBM_ENONFINITE (-5)  /* non-finite populations detected            */
-#define LBM_ENOTCONV (-6)    /* residual target not reached                */
+#define LBM_ENOTCONV (-6)    /* residual target not reached (reserved: no
+                                entry point returns it yet)                */
 
 /* ---- enumerations ---------------------------------------------------- */
 #define LBM_SOA 0            /* populations of one direction contiguous    */
