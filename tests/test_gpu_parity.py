@@ -258,8 +258,10 @@ def test_nonfinite_detected(L):
 _DIAG_FORMS = [
     {"bounce": "fullway"}, {"bounce": "halfway"},
     {"bounce": "fullway", "storage": "f32s"}, {"bounce": "halfway", "storage": "f16sr"},
+    # the AoS column march carries them too
+    {"layout": "aos", "bounce": "halfway"}, {"layout": "aos", "bounce": "fullway", "storage": "f32s"},
     # forms without a fused sweep run the two passes in turn
-    {"layout": "aos", "bounce": "halfway"}, {"addressing": "list", "bounce": "halfway"},
+    {"addressing": "list", "bounce": "halfway"},
     {"propagation": "aa", "bounce": "fullway"}, {"propagation": "push", "bounce": "halfway"},
 ]
 
