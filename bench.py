@@ -276,7 +276,8 @@ def main():
                          ("soa_f64_halfway", dict(bounce="halfway")),
                          ("aa_soa_f64", dict(propagation="aa")),
                          ("push_soa_f64", dict(propagation="push")),
-                         ("push_aos_f64", dict(propagation="push", layout="aos"))]:
+                         ("push_aos_f64", dict(propagation="push", layout="aos")),
+                         ("aa_aos_f64", dict(propagation="aa", layout="aos"))]:
             if not wanted(name):
                 continue
             log("variant %s" % name)
