@@ -398,11 +398,26 @@ k_push_aos(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ 
 // slot i of x + c_i, in place.  The reads follow the z march of the push
 // skeleton without the collision at the source: one thread per halo'd
 // position loads that node's record and sorts its slots into the class
-// regions (the slot staged for direction i is opp(i)); interior threads
-// gather, collide and store their 19 results slot by slot into the
-// neighbours' records.  Every slot is read and then written by the one node
-// that owns it, so staging whole records in place is safe: the slots of
-// other nodes that come along are never used.
+// regions (the slot staged for direction i is opp(i)).  Every slot is read
+// and then written by the one node that owns it (x reads and writes slot i
+// of x + c_i's record... as opp(i) of its source), so staging whole records
+// in place is safe: the slots of other nodes that come along are never used.
+//
+// The writes: a record receives its slots over three steps (from the nodes
+// of the layer below, its own layer and the layer above) and, at the column
+// edge, from neighbouring columns, so slot-by-slot stores reach HBM as
+// partially written lines about three times each.  Records whose 19 writers
+// all lie in this column and chunk ("inner" records: 2 .. seg-1 in x and
+// y, layers zb+1 .. ze-2) are therefore assembled in LDS instead: seeded
+// with the record as loaded (slots whose writer is a solid node keep their
+// value), filled by the writers and stored whole one step after their last
+// writer.  Only the edge records are written slot by slot.
+template <int BX, int TY>
+struct AaShape {
+  static constexpr int NI = (BX - 2) * (TY - 2);  // inner records per layer
+  static constexpr int OB = 3 * NI * Q;           // assembly ring of three layers
+};
+
 template <class ST, int BB, int BX, int TY>
 __global__ void __launch_bounds__((PushShape<BX, TY>::NT))
 k_aa_aos_odd(typename ST::T* A, const uint8_t* __restrict__ mask,
@@ -411,9 +426,10 @@ k_aa_aos_odd(typename ST::T* A, const uint8_t* __restrict__ mask,
   using T = typename ST::T;
   using R = typename ST::R;
   using S = PushShape<BX, TY>;
-  constexpr int HX = S::HX, P = S::P;
+  constexpr int HX = S::HX, P = S::P, NI = AaShape<BX, TY>::NI, IW = BX - 2;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* L = reinterpret_cast<T*>(lds_raw);
+  T* OB = L + S::STAGE;  // [3][NI][Q]
 
   const int per = gridDim.x / 8;
   const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -442,6 +458,13 @@ k_aa_aos_odd(typename ST::T* A, const uint8_t* __restrict__ mask,
   const int64_t ox[3] = {xs == 0 ? nx - 1 : -1, 0, xs == nx - 1 ? 1 - nx : 1};
   const int64_t oy[3] = {(ys == 0 ? ny - 1 : -1) * (int64_t)nx, 0,
                          (ys == ny - 1 ? 1 - ny : 1) * (int64_t)nx};
+  // inner records: halo'd position (hx, hy) and logical layer L
+  auto inner_xy = [&](int px, int py) { return px >= 2 && px <= seg - 1 && py >= 2 && py <= segy - 1; };
+  auto inner_z = [&](int zl) { return zl >= zb + 1 && zl <= ze - 2; };
+  auto ring = [&](int zl) { return (zl - zb + 3) % 3; };
+  auto ob_at = [&](int zl, int px, int py) {
+    return OB + ((int64_t)ring(zl) * NI + (py - 2) * IW + (px - 2)) * Q;
+  };
 
   T r[Q];
   uint32_t geo_next = 0;
@@ -470,6 +493,11 @@ k_aa_aos_odd(typename ST::T* A, const uint8_t* __restrict__ mask,
     const int z = zb + s;
     if (s >= 0) {
       put(0, 0);  // down slots of layer z+1
+      if (live && inner_xy(hx, hy) && inner_z(z + 1)) {  // seed its assembly
+        T* d = ob_at(z + 1, hx, hy);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = r[i];
+      }
       __syncthreads();
       const bool solid = BB == LBM_HALFWAY ? (geo_cur & 1u) != 0 : geo_cur != 0;
       R f[Q];
@@ -507,12 +535,28 @@ k_aa_aos_odd(typename ST::T* A, const uint8_t* __restrict__ mask,
         for (int i = 0; i < Q; ++i) {
           const T v = ST::store(f[i], k.scale, rs.next());
           // link bit opp(i): x + c_i is solid, the population stays home
-          if (BB == LBM_HALFWAY && i != 0 && ((lk >> Vel::opp[i]) & 1u))
-            home[Vel::opp[i]] = v;
-          else
-            home[(ox[Vel::cx[i] + 1] + oy[Vel::cy[i] + 1] + oz[Vel::cz[i] + 1]) * Q + i] = v;
+          if (BB == LBM_HALFWAY && i != 0 && ((lk >> Vel::opp[i]) & 1u)) {
+            if (inner_xy(hx, hy) && inner_z(z)) ob_at(z, hx, hy)[Vel::opp[i]] = v;
+            else home[Vel::opp[i]] = v;
+          } else {
+            const int px = hx + Vel::cx[i], py = hy + Vel::cy[i], zl = z + Vel::cz[i];
+            if (inner_xy(px, py) && inner_z(zl)) ob_at(zl, px, py)[i] = v;
+            else home[(ox[Vel::cx[i] + 1] + oy[Vel::cy[i] + 1] + oz[Vel::cz[i] + 1]) * Q + i] = v;
+          }
         }
       }
+      // the records of layer z-1 have had their last writers: store them
+      __syncthreads();
+      if (inner_z(z - 1) && t < NI) {
+        const int px = t % IW + 2, py = t / IW + 2;
+        if (px <= seg - 1 && py <= segy - 1) {
+          const T* src = ob_at(z - 1, px, py);
+          T* dst = A + ((wrapz(z - 1) * plane_nodes) + (int64_t)(y0 + py - 1) * nx + (x0 + px - 1)) * Q;
+#pragma unroll
+          for (int i = 0; i < Q; ++i) dst[i] = src[i];
+        }
+      }
+      __syncthreads();  // the next step seeds this ring slot again
     } else {
       // s = -2: up slots of layer zb-1 (set 0); s = -1: level and up slots
       // of layer zb (set 1)
@@ -608,25 +652,33 @@ hipError_t launch_pull_aos_diag(lbm_ctx* c, const void* src, void* dst, int resi
   });
 }
 
+template <class ST, int BX, int TY>
+static hipError_t launch_aa_aos_odd_t(lbm_ctx* c, void* buf) {
+  using T = typename ST::T;
+  using S = PushShape<BX, TY>;
+  const lbm_params& p = c->p;
+  const auto k = make_collide<typename ST::R>(p, c->step);
+  int zc, n_tiles;
+  unsigned grid;
+  march_grid(p, BX, TY, zc, n_tiles, grid);
+  const size_t lds = sweep_lds(c, (size_t)(S::STAGE + AaShape<BX, TY>::OB) * sizeof(T));
+  if (p.bounce == LBM_FULLWAY)
+    hipLaunchKernelGGL((k_aa_aos_odd<ST, LBM_FULLWAY, BX, TY>), dim3(grid), dim3(S::NT), lds,
+                       c->stream, (T*)buf, c->b.mask, c->b.links, p.nx, p.ny, p.nz, zc, n_tiles, k);
+  else
+    hipLaunchKernelGGL((k_aa_aos_odd<ST, LBM_HALFWAY, BX, TY>), dim3(grid), dim3(S::NT), lds,
+                       c->stream, (T*)buf, c->b.mask, c->b.links, p.nx, p.ny, p.nz, zc, n_tiles, k);
+  return hipGetLastError();
+}
+
+// Column shapes as measured at 512^3 (neighbour step, full-way / half-way):
+// FP64 64 x 4 (15.5 / 17.4 ms; 32 x 8: 16.2 / 18.0; 16 x 8: 16.7 / 17.3),
+// the 4- and 2-byte storages 16 x 8 (FP32 9.4 / 9.5 ms; 32 x 8: 10.1 / 11.3).
 hipError_t launch_aa_aos_odd(lbm_ctx* c, void* buf) {
   return with_storage(c->p, [&](auto st) -> hipError_t {
     using ST = decltype(st);
-    using T = typename ST::T;
-    constexpr int BX = kAosBX, TY = kAosTY;
-    using S = PushShape<BX, TY>;
-    const lbm_params& p = c->p;
-    const auto k = make_collide<typename ST::R>(p, c->step);
-    int zc, n_tiles;
-    unsigned grid;
-    march_grid(p, BX, TY, zc, n_tiles, grid);
-    const size_t lds = sweep_lds(c, (size_t)S::STAGE * sizeof(T));
-    if (p.bounce == LBM_FULLWAY)
-      hipLaunchKernelGGL((k_aa_aos_odd<ST, LBM_FULLWAY, BX, TY>), dim3(grid), dim3(S::NT), lds,
-                         c->stream, (T*)buf, c->b.mask, c->b.links, p.nx, p.ny, p.nz, zc, n_tiles, k);
-    else
-      hipLaunchKernelGGL((k_aa_aos_odd<ST, LBM_HALFWAY, BX, TY>), dim3(grid), dim3(S::NT), lds,
-                         c->stream, (T*)buf, c->b.mask, c->b.links, p.nx, p.ny, p.nz, zc, n_tiles, k);
-    return hipGetLastError();
+    if (sizeof(typename ST::T) == 8) return launch_aa_aos_odd_t<ST, 64, 4>(c, buf);
+    return launch_aa_aos_odd_t<ST, 16, 8>(c, buf);
   });
 }
 
