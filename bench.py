@@ -209,21 +209,46 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline():
-    """The oracle (single-threaded C, as it stands) on a bounded sample of
-    the headline workload: a 16-node-long section of the same 512 x 512
-    channel cross-section (the duct flow is x-invariant, so every node does
-    the same work), 12 updates."""
+    """The oracle (plain C, as it stands) on bounded samples of the headline
+    workload: sections of the same 512 x 512 channel cross-section (the duct
+    flow is x-invariant, so every node does the same work), 12 updates each.
+    Timed twice: the serial build on one core, and the OpenMP build of the
+    same source (a parallel loop over nodes, identical results) on all the
+    host cores this process may use (OMP_NUM_THREADS if set)."""
+    threads = int(os.environ.get("OMP_NUM_THREADS") or 0) or len(os.sched_getaffinity(0))
+    os.environ["OMP_NUM_THREADS"] = str(threads)  # read when the OpenMP build loads
     from oracle import oracle as O
     from paper_1711_11468_amd import inputs as I
-    mask = I.channel_mask(16, 512, 512)
     steps = 12
-    secs = O.time_run(mask, steps, PHYS["tau_plus"], PHYS["magic"], PHYS["g"], 0)
-    nf = int((mask == 0).sum())
-    return {"value": round(nf * steps / secs / 1e6, 3), "unit": "MFLUP/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "channel 16x512x512 (same cross-section as 512^3), %d updates, %.1f s, %s"
-                      % (steps, secs, platform.processor() or platform.machine())}
+    rows = {}
+    for key, nx, omp in (("serial", 16, False), ("openmp", 64, True)):
+        mask = I.channel_mask(nx, 512, 512)
+        secs = O.time_run(mask, steps, PHYS["tau_plus"], PHYS["magic"], PHYS["g"], 0, omp=omp)
+        nf = int((mask == 0).sum())
+        rows[key] = (nf * steps / secs / 1e6, secs, nx)
+        del mask
+    model = cpu_model()
+    v, secs, nx = rows["openmp"]
+    v1, secs1, nx1 = rows["serial"]
+    log("cpu baseline: %.2f MFLUP/s on %d threads, %.2f on one (%s)" % (v, threads, v1, model))
+    return {"value": round(v, 3), "unit": "MFLUP/s", "cores": threads, "kind": "oracle",
+            "sample": "channel %dx512x512 (same cross-section as 512^3), %d updates, %.1f s, "
+                      "OpenMP build on %d threads; serial build: channel %dx512x512, %d updates, "
+                      "%.1f s" % (nx, steps, secs, threads, nx1, steps, secs1),
+            "single_thread_value": round(v1, 3), "nproc": os.cpu_count(), "cpu_model": model}
 
 
 def main():

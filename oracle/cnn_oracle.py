@@ -2,7 +2,9 @@
 
 Plain PyTorch CPU operations in float64: ``conv3d`` on circularly padded
 input, leaky ReLU, nearest-neighbour upsampling, concatenation, masked mean
-squared error, with gradients from autograd.  It shares no code with the
+squared error, with gradients from autograd; the Adam update written out
+from its definition (Kingma and Ba, "Adam: A Method for Stochastic
+Optimization", 2015, Algorithm 1) in float64 numpy.  It shares no code with the
 GPU kernels; it takes the same weights (rounded to bf16 by the caller when
 comparing with the bf16 kernels) in the layout [taps][c_out][c_in] and
 channels-last activations [B][D][H][W][C].
@@ -67,3 +69,29 @@ def masked_mse(pred, target, fluid):
 def bf16_round(t):
     """Round float64 values to bf16 (round to nearest even) and back."""
     return t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+
+def adam_step(param, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update in float64 (Kingma and Ba, Algorithm 1): the biased
+    first and second moment estimates m <- beta1 m + (1 - beta1) g and
+    v <- beta2 v + (1 - beta2) g^2, their bias corrections
+    m_hat = m / (1 - beta1^t) and v_hat = v / (1 - beta2^t), and the step
+    param <- param - lr m_hat / (sqrt(v_hat) + eps).  t >= 1 is the index of
+    this update.  Returns (param, m, v) as new float64 arrays."""
+    import numpy as np
+    p = np.asarray(param, dtype=np.float64)
+    g = np.asarray(grad, dtype=np.float64)
+    m_new = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v_new = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m_new / (1.0 - beta1 ** t)
+    v_hat = v_new / (1.0 - beta2 ** t)
+    return p - lr * m_hat / (np.sqrt(v_hat) + eps), m_new, v_new
+
+
+def bf16_bits_rne(x):
+    """bfloat16 bit patterns (uint16) of float32 values, round to nearest
+    even, by integer arithmetic on the float32 bits (finite inputs)."""
+    import numpy as np
+    b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    rounded = (b + 0x7FFF + ((b >> 16) & 1)) >> 16
+    return rounded.astype(np.uint16)

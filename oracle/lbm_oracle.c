@@ -30,6 +30,12 @@
  *   - The lattice is a 3-torus: every axis wraps; walls are solid nodes of
  *     the mask (Sect. 2 geometries include their wall layers).
  *
+ * Threads: the two passes carry OpenMP "parallel for" pragmas over nodes
+ * (collide) and over z planes (stream).  A plain build ignores them; the
+ * OpenMP build is used only to time the oracle on all host cores.  Each
+ * node's arithmetic, and each slot's single writer, is the same in both
+ * builds, so their results are identical bit for bit.
+ *
  * State layout: canonical pre-collision populations f[node][19] in double
  * precision, node = x + nx*(y + ny*z).  With half-way bounce-back solid
  * nodes carry no state and are kept at zero.
@@ -178,7 +184,9 @@ int ora_run(int nx, int ny, int nz, const uint8_t* mask, int bounce,
   double* post = (double*)malloc(sizeof(double) * ORA_Q * n_nodes);
   if (!post) return -1;
   for (int step = 0; step < nsteps; ++step) {
-    /* collide */
+    /* collide (the OpenMP build splits the nodes over threads; every
+       node's arithmetic is the same in either build) */
+#pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < n_nodes; ++n) {
       const double* fn = f + ORA_Q * n;
       double* pn = post + ORA_Q * n;
@@ -192,6 +200,9 @@ int ora_run(int nx, int ny, int nz, const uint8_t* mask, int bounce,
     }
     /* stream */
     if (bounce == 1) memset(f, 0, sizeof(double) * ORA_Q * n_nodes);
+    /* each target slot has one writer: f(x + c_i, i) from x, or, for a
+       solid target under half-way bounce-back, f(x, opp i) from x itself */
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z)
       for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {

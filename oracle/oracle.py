@@ -29,27 +29,36 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _BUILD = os.path.join(_HERE, "_build")
 _LIB = os.path.join(_BUILD, "liblbm_oracle.so")
+_LIB_OMP = os.path.join(_BUILD, "liblbm_oracle_omp.so")
 
 Q = 19
-_lib = None
+_libs = {}
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, no FP contraction, no fast-math)."""
-    os.makedirs(_BUILD, exist_ok=True)
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
+def _build_one(out: str, extra, force: bool) -> str:
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
         subprocess.check_call([
             "gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-            "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+            "-fno-fast-math", *extra, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        lib = ctypes.CDLL(build())
+def build(force: bool = False, omp: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no FP contraction, no fast-math);
+    ``omp``: the OpenMP build of the same source (used for timing on all
+    cores; identical results).  ``force`` rebuilds both."""
+    os.makedirs(_BUILD, exist_ok=True)
+    serial = _build_one(_LIB, [], force)
+    par = _build_one(_LIB_OMP, ["-fopenmp"], force) if (omp or force) else None
+    return par if omp else serial
+
+
+def _load(omp: bool = False):
+    lib = _libs.get(omp)
+    if lib is None:
+        lib = ctypes.CDLL(build(omp=omp))
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -65,8 +74,8 @@ def _load():
         lib.ora_run.restype = ctypes.c_int
         lib.ora_macroscopic.argtypes = [ctypes.c_int64, u8p, dp, dp, dp, dp]
         lib.ora_rest_state.argtypes = [ctypes.c_int64, u8p, ctypes.c_int, dp]
-        _lib = lib
-    return _lib
+        _libs[omp] = lib
+    return lib
 
 
 def _dp(a):
@@ -112,15 +121,16 @@ def rest_state(mask: np.ndarray, bounce: int) -> np.ndarray:
 
 
 def run(mask: np.ndarray, f: np.ndarray, steps: int, tau_plus: float,
-        magic: float, g, bounce: int) -> np.ndarray:
+        magic: float, g, bounce: int, omp: bool = False) -> np.ndarray:
     """Advance a copy of the canonical state ``f`` by ``steps`` updates.
 
-    bounce: 0 = full-way, 1 = half-way."""
+    bounce: 0 = full-way, 1 = half-way.  ``omp``: run the OpenMP build
+    (threads from OMP_NUM_THREADS; same results bit for bit)."""
     m = np.ascontiguousarray(mask, dtype=np.uint8)
     nz, ny, nx = m.shape
     out = np.array(f, dtype=np.float64, order="C", copy=True).reshape(m.size, Q)
     gg = np.ascontiguousarray(g, dtype=np.float64)
-    rc = _load().ora_run(nx, ny, nz, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+    rc = _load(omp).ora_run(nx, ny, nz, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                          bounce, tau_plus, magic, _dp(gg), _dp(out), steps)
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
@@ -147,7 +157,7 @@ def residual(u_new: np.ndarray, u_old: np.ndarray, fluid: np.ndarray) -> float:
 
 
 def run_to_steady(mask, f, tau_plus, magic, g, bounce, tol, check_every=100,
-                  max_steps=10_000_000):
+                  max_steps=10_000_000, omp=False):
     """Iterate in chunks of ``check_every`` until the velocity residual
     between chunks falls below ``tol``.  Returns (f, steps, residual)."""
     fluid = np.asarray(mask).reshape(-1) == 0
@@ -155,7 +165,7 @@ def run_to_steady(mask, f, tau_plus, magic, g, bounce, tol, check_every=100,
     steps = 0
     r = float("inf")
     while steps < max_steps:
-        f = run(mask, f, check_every, tau_plus, magic, g, bounce)
+        f = run(mask, f, check_every, tau_plus, magic, g, bounce, omp=omp)
         steps += check_every
         _, u = macroscopic(mask, f, g)
         r = residual(u, u_old, fluid)
@@ -216,10 +226,11 @@ def duct_series(ny: int, nz: int, nu: float, gx: float, terms: int = 201) -> np.
     return u
 
 
-def time_run(mask, steps, tau_plus, magic, g, bounce):
+def time_run(mask, steps, tau_plus, magic, g, bounce, omp=False):
     """Wall-clock seconds of ``steps`` oracle updates from the rest state
-    (single thread).  Used for the CPU baseline figure."""
+    (single thread, or the OpenMP build with OMP_NUM_THREADS threads).
+    Used for the CPU baseline figure."""
     f = rest_state(mask, bounce)
     t0 = time.perf_counter()
-    run(mask, f, steps, tau_plus, magic, g, bounce)
+    run(mask, f, steps, tau_plus, magic, g, bounce, omp=omp)
     return time.perf_counter() - t0

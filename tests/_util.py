@@ -52,3 +52,14 @@ def oracle_window_sample(mask, center, steps, f0_full=None, bounce="fullway", **
     c = steps
     w = 2 * steps + 1
     return f[c + w * (c + w * c)]
+
+
+def golden_duct130(name):
+    """Full 130 x 130 cross-section u_x[z][y] of a duct fixture in
+    tests/golden/ (stored as the quadrant y, z = 0..64; the duct is
+    mirror-symmetric in y and z)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    q = np.loadtxt(path)
+    top = np.concatenate([q, q[:, ::-1]], axis=1)
+    return np.concatenate([top, top[::-1, :]], axis=0)

@@ -79,3 +79,59 @@ def test_unet_gradient_finite_differences():
             fd = (lp - lm) / (2 * h)
             ad = w.grad[idx].item()
             assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-3), (name, idx, fd, ad)
+
+
+def test_adam_first_step_closed_form():
+    """From zero moments the first update is -lr g / (|g| + eps): the bias
+    corrections undo the (1 - beta) factors exactly."""
+    rng = np.random.default_rng(0)
+    p = rng.normal(size=50)
+    g = rng.normal(size=50) * 10.0 ** rng.uniform(-6, 2, size=50)
+    out, m, v = R.adam_step(p, g, np.zeros(50), np.zeros(50), 1, lr=1e-3)
+    np.testing.assert_allclose(out - p, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-18)
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-15)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-13)
+
+
+def test_adam_constant_gradient_every_step():
+    """With a constant gradient the bias-corrected moments equal g and g^2
+    at every step, so every update is -lr g / (|g| + eps)."""
+    g = np.array([2.0, -0.5, 1e-3, -7.0])
+    p = np.zeros(4)
+    m = np.zeros(4)
+    v = np.zeros(4)
+    for t in range(1, 8):
+        new, m, v = R.adam_step(p, g, m, v, t, lr=0.01, beta1=0.8, beta2=0.99)
+        np.testing.assert_allclose(new - p, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+        p = new
+
+
+def test_adam_matches_torch_optimizer():
+    """Five updates with changing gradients agree with torch.optim.Adam
+    (float64, CPU), an independent implementation of the same algorithm."""
+    rng = np.random.default_rng(1)
+    p0 = rng.normal(size=64)
+    grads = [rng.normal(size=64) * s for s in (1.0, 0.3, 3.0, 1e-3, 0.5)]
+    w = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([w], lr=2e-3, betas=(0.9, 0.999), eps=1e-8)
+    p, m, v = p0.copy(), np.zeros(64), np.zeros(64)
+    for t, g in enumerate(grads, start=1):
+        w.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        p, m, v = R.adam_step(p, g, m, v, t, lr=2e-3)
+        np.testing.assert_allclose(p, w.detach().numpy(), rtol=1e-14, atol=1e-16)
+
+
+def test_bf16_rounding_bits():
+    """The integer round-to-nearest-even to bf16 agrees with torch's
+    conversion, including exact ties, and keeps exactly representable
+    values."""
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -1.0 - 2 ** -8, 3.1415926, -2.5e-7,
+                     1.0 + 2 ** -7, 65504.0, 1e30], dtype=np.float32)
+    rng = np.random.default_rng(5)
+    vals = np.concatenate([vals, rng.normal(size=1000).astype(np.float32) * 10.0])
+    want = torch.from_numpy(vals).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(R.bf16_bits_rne(vals), want)
+    # ties go to even: 1 + 2^-8 lies halfway between 1 and 1 + 2^-7
+    assert R.bf16_bits_rne(np.float32(1.0 + 2 ** -8)) == 0x3F80
+    assert R.bf16_bits_rne(np.float32(1.0 + 3 * 2 ** -8)) == 0x3F82

@@ -493,3 +493,64 @@ def test_ria_and_list_agree(L):
             a.step(5)
             b.step(5)
             assert rel_maxabs(a.export(), b.export()) <= 1e-15, prop
+
+
+# the forms the kernel study times on the `blocks` geometry (and the AoS
+# forms it times on the channel)
+STUDY_FORMS = [
+    {}, {"bounce": "halfway"}, {"propagation": "push"},
+    {"addressing": "list", "bounce": "halfway"},
+    {"addressing": "list", "bounce": "halfway", "propagation": "push"},
+    {"addressing": "ria", "bounce": "halfway"},
+    {"propagation": "aa"},
+    {"addressing": "list", "bounce": "halfway", "propagation": "aa"},
+    {"addressing": "ria", "bounce": "halfway", "propagation": "aa"},
+    {"layout": "aos"}, {"addressing": "list", "bounce": "halfway", "layout": "aos"},
+]
+
+
+@pytest.mark.parametrize("kw", STUDY_FORMS)
+@pytest.mark.parametrize("edge", [1, 2, 3])
+def test_blocks_geometry_whole_domain(L, kw, edge):
+    """The `blocks` geometry (cubic obstacles of edge b, gap b, inside the
+    channel walls; the paper's Fig. 4 study) in every form the kernel study
+    times: the whole state against the oracle after an odd number of
+    updates."""
+    mask = I.blocks_mask(61, 14, 13, block=edge, gap=edge)
+    assert 0 < int(mask.sum()) < mask.size
+    got, ref, _ = _case(mask, 11, L, **kw)
+    assert rel_maxabs(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("kw", STUDY_FORMS[:9])
+@pytest.mark.parametrize("edge", [1, 4, 16])
+def test_blocks_study_size_sampled(L, kw, edge):
+    """The study's own size (500 x 100 x 100, edges 1, 4, 16): fluid nodes
+    next to obstacle faces, edges and corners and in the gaps, against the
+    windowed oracle after 8 updates."""
+    steps = 8
+    mask = I.blocks_mask(500, 100, 100, block=edge, gap=edge)
+    phys = dict(tau_plus=0.8, magic=3 / 16, g=(1e-6, 0.0, 0.0))
+    lat = L.Lattice(mask, **phys, **kw)
+    lat.step(steps)
+    fluid = mask == 0
+    solid = ~fluid
+    # fluid nodes with a solid neighbour among the 18 links, off the walls
+    near = np.zeros_like(fluid)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if abs(dx) + abs(dy) + abs(dz) in (1, 2):
+                    near |= np.roll(solid, (dz, dy, dx), axis=(0, 1, 2))
+    near &= fluid
+    near[:, :2, :] = near[:, -2:, :] = False
+    near[:2, :, :] = near[-2:, :, :] = False
+    rng = np.random.default_rng(edge)
+    ids = np.concatenate([rng.choice(np.flatnonzero(near.reshape(-1)), 10, replace=False),
+                          rng.choice(np.flatnonzero(fluid.reshape(-1)), 4, replace=False)])
+    got = lat.export(ids)
+    bounce = kw.get("bounce", "fullway")
+    for k, lin in enumerate(ids):
+        c = (int(lin % 500), int((lin // 500) % 100), int(lin // 50000))
+        ref = oracle_window_sample(mask, c, steps, bounce=bounce, **phys)
+        assert rel_maxabs(got[k], ref) <= TOL, (c, kw)

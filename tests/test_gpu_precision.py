@@ -143,3 +143,102 @@ def test_equal_step_error_every_form(L, storage, tol, form):
     v = lat.verify(L.VERIFY_REFERENCE, torch.from_numpy(ref.reshape(-1)).to(lat.device))
     print(storage, kw, v)
     assert v["rel_l2"] <= tol
+
+
+# ---- the benchmarked shape: 512^3 channel, the bench's launch shape -------
+
+@pytest.fixture(scope="module")
+def section512():
+    """The oracle's state of the 512^3 channel after 110 updates from rest,
+    from its x-invariant cross-section (one node thick: with a uniform
+    start and x-periodicity the duct flow does not depend on x).  Returns
+    (f [512*512][19], u [512*512][3]) indexed by y + 512 z."""
+    m1 = I.channel_mask(1, 512, 512)
+    f = O.run(m1, O.rest_state(m1, 0), 110, PHYS["tau_plus"], PHYS["magic"], PHYS["g"], 0,
+              omp=True)
+    return f, O.macroscopic(m1, f, PHYS["g"])[1]
+
+
+@pytest.fixture(scope="module")
+def mask512():
+    return I.channel_mask(512, 512, 512)
+
+
+@pytest.mark.parametrize("layout", ["soa", "aos"])
+@pytest.mark.parametrize("storage,tol_u,tol_h", [("f32s", 1e-5, 1e-4), ("f16s", 1e-2, 5e-2),
+                                                 ("f16sr", 1e-2, 5e-2)])
+def test_full_size_shifted_channel_512(L, section512, mask512, layout, storage, tol_u, tol_h):
+    """Shifted FP32/FP16 storage at 512^3 in the benchmark's launch
+    configuration (the form and shape whose speed-up is reported): after
+    110 updates, the relative L2 velocity error over all 133 M fluid nodes
+    against the FP64 oracle, and the error of the flow part f - w of the
+    populations on sampled nodes (relative to its max) against the
+    oracle's populations."""
+    import torch
+    n = 512
+    f_ref, u_ref = section512
+    lat = L.Lattice(mask512, storage=storage, layout=layout, **PHYS)
+    lat.step(110)
+    ref = torch.from_numpy(np.ascontiguousarray(u_ref.T)).to(lat.device)
+    ref = ref.view(3, n, n, 1).expand(3, n, n, n).contiguous().view(-1)
+    v = lat.verify(L.VERIFY_REFERENCE, ref)
+    del ref
+    rng = np.random.default_rng(5)
+    yz = rng.integers(1, n - 1, size=(48, 2))
+    xs = rng.integers(0, n, size=48)
+    ids = xs + n * (yz[:, 0] + n * yz[:, 1])
+    got = lat.export(ids)
+    want = f_ref[yz[:, 0] + n * yz[:, 1]]
+    _, w, _ = O.table()
+    h_err = float(np.abs(got - want).max() / np.abs(want - w).max())
+    print("512^3 %s %s: u rel-L2 %.3e (max-abs %.3e of %.3e), f-w rel max-abs %.3e"
+          % (layout, storage, v["rel_l2"], v["max_abs"], v["ref_max"], h_err))
+    assert v["n_compared"] == int((mask512 == 0).sum())
+    assert v["rel_l2"] <= tol_u
+    assert h_err <= tol_h
+
+
+# ---- mid-size duct to steady state (130 x 130 cross-section) -------------
+
+def _duct130_ref(name, nx, device):
+    import torch
+    from tests._util import golden_duct130
+    ux = golden_duct130(name)
+    ref = np.zeros((3, 130, 130, nx))
+    ref[0] = ux[:, :, None]
+    return torch.from_numpy(ref.reshape(-1)).to(device)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-9), ("f32s", 1e-5), ("f16sr", 1e-3)])
+def test_midsize_duct_equal_step_error(L, storage, tol):
+    """64 x 130 x 130 duct after exactly 20,000 updates against the oracle
+    after the same number (tests/golden/duct130_step20000.txt): the
+    storage rounding alone, at a flow that is already close to steady.
+    Half-way bounce-back, as in the fixture."""
+    mask = I.channel_mask(64, 130, 130)
+    lat = L.Lattice(mask, storage=storage, bounce="halfway", **PHYS)
+    lat.step(20000)
+    v = lat.verify(L.VERIFY_REFERENCE, _duct130_ref("duct130_step20000.txt", 64, lat.device))
+    print("duct130 %s after 20000 updates: u rel-L2 %.3e" % (storage, v["rel_l2"]))
+    assert v["rel_l2"] <= tol
+
+
+@pytest.mark.parametrize("storage,target,tol", [("f64", 1e-9, 1e-6), ("f32s", 1e-8, 1e-5),
+                                                ("f16sr", 1e-6, 1e-3)])
+def test_midsize_duct_steady_error(L, storage, target, tol):
+    """64 x 130 x 130 duct run to steady state against the converged oracle
+    (tests/golden/duct130_steady.txt, residual < 1e-10).  The slowest duct
+    mode decays over ~8,300 updates, so at a residual r per 100 updates
+    the remaining iteration error is ~83 r: FP64 and FP32 therefore run to
+    a tighter residual than 1e-6; the shifted storages may instead stop
+    at their residual plateau (FP16 with stochastic rounding: its storage
+    noise).  Half-way bounce-back, as in the fixture (the steady states of
+    the two bounce-back kinds agree; their transients do not)."""
+    mask = I.channel_mask(64, 130, 130)
+    lat = L.Lattice(mask, storage=storage, bounce="halfway", **PHYS)
+    steps, r, why = lat.run_to_steady(target, max_steps=600000, plateau_checks=30)
+    v = lat.verify(L.VERIFY_REFERENCE, _duct130_ref("duct130_steady.txt", 64, lat.device))
+    print("duct130 %s steady: %d steps, residual %.2e (%s), u rel-L2 %.3e"
+          % (storage, steps, r, why, v["rel_l2"]))
+    assert why in (("converged",) if storage == "f64" else ("converged", "plateau"))
+    assert v["rel_l2"] <= tol

@@ -61,14 +61,13 @@ def test_planted_mistake_is_caught(name, tmp_path, monkeypatch):
     so = tmp_path / "libmutant.so"
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
                            "-ffp-contract=off", "-o", str(so), str(mutant), "-lm"])
-    O._load()  # make sure the real library's argtypes are known
-    real = O._lib
+    real = O._load()  # the real library, whose argtypes are set
     lib = ctypes.CDLL(str(so))
     for fn in ("ora_table", "ora_equilibrium", "ora_moments", "ora_collide_node",
                "ora_tau_minus", "ora_run", "ora_macroscopic", "ora_rest_state"):
         getattr(lib, fn).argtypes = getattr(real, fn).argtypes
         getattr(lib, fn).restype = getattr(real, fn).restype
-    monkeypatch.setattr(O, "_lib", lib)
+    monkeypatch.setitem(O._libs, False, lib)
     failed = []
     for fn, kw in FAST_PINS:
         try:

@@ -280,3 +280,21 @@ def test_slab_profile_reference_values():
     q = O.slab_profile(nz, tp, 1 / 4, gx)
     np.testing.assert_allclose(q[1:-1] - p[1:-1], gx / (24 * nu), rtol=1e-12)
     np.testing.assert_allclose(p.max(), gx / (2 * nu) * (16 - 0.25), rtol=1e-14)
+
+
+@pytest.mark.parametrize("bounce", [0, 1])
+def test_openmp_build_identical(bounce, monkeypatch):
+    """The OpenMP build (used only to time the oracle on all cores) splits
+    the node loops over threads without changing any node's arithmetic: its
+    states equal the serial build's bit for bit."""
+    monkeypatch.setenv("OMP_NUM_THREADS", "4")
+    mask = I.random_solid_mask(13, 11, 9, seed=4, fraction=0.25)
+    f0 = O.rest_state(mask, bounce)
+    rng = np.random.default_rng(2)
+    f0 = f0 * (1.0 + 0.02 * rng.uniform(-1, 1, f0.shape))
+    if bounce == 1:
+        f0[mask.reshape(-1) != 0] = 0.0
+    g = (1e-4, -3e-5, 2e-5)
+    a = O.run(mask, f0, 9, 0.9, 3 / 16, g, bounce)
+    b = O.run(mask, f0, 9, 0.9, 3 / 16, g, bounce, omp=True)
+    assert np.array_equal(a, b)
