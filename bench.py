@@ -106,21 +106,31 @@ def membench(lat, reps=20):
     n = int(s.n_sites)
     stride = int(s.stride)
     out = {}
-    names = {0: "copy", 1: "copy-19", 2: "copy-19-nt", 3: "update-19"}
-    for kind, name in names.items():
-        nn = n * 19 if kind == 0 else n
+    # kind: (name, threads per workgroup, accesses per element: 2 = read and
+    # write, 1 = read or write only)
+    kinds = {0: ("copy", 256, 2), 1: ("copy-19", 256, 2), 2: ("copy-19-nt", 256, 2),
+             3: ("update-19", 256, 2), 4: ("copy-v", 256, 2), 5: ("copy-4-v", 256, 2),
+             6: ("copy-19-v", 256, 2), 7: ("copy-19-vp", 256, 2), 8: ("read-19-v", 256, 1),
+             9: ("write-19-v", 256, 1)}
+    for kind, (name, block, acc) in kinds.items():
+        nn = n * 19 if kind in (0, 4) else n
+        st = stride
+        if kind == 5:  # four arrays spanning the same buffers
+            st = stride * 19 // 4 // 2 * 2
+            nn = st
+        src = None if kind == 9 else a
         for _ in range(3):
-            lbm.membench(kind, a, b, nn, stride, 256, lat.stream.cuda_stream)
+            lbm.membench(kind, src, b, nn, st, block, lat.stream.cuda_stream)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(lat.stream)
         for _ in range(reps):
-            lbm.membench(kind, a, b, nn, stride, 256, lat.stream.cuda_stream)
+            lbm.membench(kind, src, b, nn, st, block, lat.stream.cuda_stream)
         e1.record(lat.stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        moved = 2.0 * 8 * n * 19  # one read and one write of every element
-        out[name] = round(moved / (ms * 1e-3) / 1e9, 1)
+        elems = nn * (4 if kind == 5 else (1 if kind in (0, 4) else 19))
+        out[name] = round(acc * 8.0 * elems / (ms * 1e-3) / 1e9, 1)
     return out
 
 

@@ -87,7 +87,9 @@ extern "C" {
                                 table entry; no per-node adjacency         */
 
 #define LBM_F64 0            /* double populations (the paper's storage)   */
-#define LBM_F32_SHIFTED 1    /* float  h = f - w, float collide            */
+#define LBM_F32_SHIFTED 1    /* float  h = f - w, double collide, store
+                                rounded stochastically (hash of node,
+                                direction, step)                           */
 #define LBM_F16_SHIFTED 2    /* _Float16 h = (f - w) * 2^s, float collide,
                                 round to nearest even on store             */
 #define LBM_F16_SHIFTED_SR 3 /* as LBM_F16_SHIFTED, stochastic rounding on
@@ -319,8 +321,20 @@ const char* lbm_last_error(void);
  *   kind 2 copy-19-nt:  as kind 1 with non-temporal stores;
  *   kind 3 update-19:   19 arrays of n doubles updated in place,
  *                       a_i[k] = a_i[k] * 1.0.
- * a and b are device buffers of 19*stride doubles (kinds 1-3; kind 0 uses
- * the first n).  Errors: EINVAL, EDEVICE. */
+ * Kinds 0-3 move one 8-byte element per thread.  Kinds 4-9 bound the
+ * attainable bandwidth of the same stream counts: 16-byte accesses,
+ * several in flight per thread, non-temporal stores:
+ *   kind 4 copy-v:      one array of n doubles (as kind 0);
+ *   kind 5 copy-4-v:    4 arrays of n doubles;
+ *   kind 6 copy-19-v:   19 arrays of n doubles;
+ *   kind 7 copy-19-vp:  as kind 6 on a persistent grid (8 workgroups per
+ *                       compute unit, grid-stride loop);
+ *   kind 8 read-19-v:   19 arrays of n doubles read (b untouched for
+ *                       finite data);
+ *   kind 9 write-19-v:  19 arrays of n doubles written (a unused).
+ * Kinds 4-9 need even n and stride and 16-byte aligned a and b.
+ * a and b are device buffers of 19*stride doubles (kinds 1-3, 5-9; kinds
+ * 0 and 4 use the first n).  Errors: EINVAL, EDEVICE. */
 int lbm_membench(int32_t kind, const double* a, double* b, int64_t n,
                  int64_t stride, int32_t block, void* stream);
 

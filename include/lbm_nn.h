@@ -94,9 +94,12 @@ int nn_masked_mse(const float* pred, const float* target, const uint8_t* mask, i
                   uint16_t* dy, float* loss, float* workspace, void* stream);
 
 /* Adam step (Kingma and Ba) on float32 master weights; writes the bf16
- * copy used by the kernels.  t >= 1 is the step number. */
+ * copy used by the kernels.  t >= 1 is the step number.  The
+ * hyper-parameters are double: the complements 1 - beta and the bias
+ * corrections 1 - beta^t are formed in double on the host, then the update
+ * runs in float32.  Requires 0 <= beta < 1 and eps > 0, else -1. */
 int nn_adam_step(float* param, const float* grad, float* m, float* v, uint16_t* param_bf16,
-                 int64_t n, float lr, float beta1, float beta2, float eps, int32_t t,
+                 int64_t n, double lr, double beta1, double beta2, double eps, int32_t t,
                  void* stream);
 
 /* Network input from a solid mask: x[n][c_pad] bf16 with channel 0 = solid

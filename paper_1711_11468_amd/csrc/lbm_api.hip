@@ -664,8 +664,12 @@ void lbm_destroy(lbm_ctx* c) { delete c; }
 
 int lbm_membench(int32_t kind, const double* a, double* b, int64_t n, int64_t stride, int32_t block,
                  void* stream) {
-  if (kind < 0 || kind > 3 || !b || (kind != 3 && !a) || n <= 0) { set_error("bad membench arguments"); return LBM_EINVAL; }
-  if (kind != 0 && stride < n) { set_error("stride must be >= n"); return LBM_EINVAL; }
+  if (kind < 0 || kind > 9 || !b || (kind != 3 && kind != 9 && !a) || n <= 0) { set_error("bad membench arguments"); return LBM_EINVAL; }
+  if (kind != 0 && kind != 4 && stride < n) { set_error("stride must be >= n"); return LBM_EINVAL; }
+  if (kind >= 4 && (n % 2 || stride % 2 || ((uintptr_t)a | (uintptr_t)b) % 16)) {
+    set_error("membench kinds 4-9 need even n and stride and 16-byte aligned arrays");
+    return LBM_EINVAL;
+  }
   if (block < 64 || block > 1024 || block % 64) { set_error("bad block"); return LBM_EINVAL; }
   LBM_HIP(launch_membench(kind, a, b, n, stride, block, (hipStream_t)stream), "membench launch");
   return LBM_OK;

@@ -9,6 +9,8 @@
 // 4 consecutive K elements of a lane 8 contiguous bytes.
 #include <stdint.h>
 
+#include <cmath>
+
 #include "../../include/lbm_nn.h"
 #include "internal.hpp"
 
@@ -651,12 +653,12 @@ __global__ void k_mse_grad(const float* __restrict__ pred, const float* __restri
 
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ gr, float* __restrict__ m,
                        float* __restrict__ v, uint16_t* __restrict__ pb, int64_t n, float lr,
-                       float b1, float b2, float eps, float c1, float c2) {
+                       float b1, float a1, float b2, float a2, float eps, float c1, float c2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float g = gr[i];
-  const float mi = b1 * m[i] + (1.f - b1) * g;
-  const float vi = b2 * v[i] + (1.f - b2) * g * g;
+  const float mi = b1 * m[i] + a1 * g;
+  const float vi = b2 * v[i] + a2 * g * g;
   m[i] = mi;
   v[i] = vi;
   const float mh = mi / c1, vh = vi / c2;
@@ -1037,15 +1039,20 @@ int nn_masked_mse(const float* pred, const float* target, const uint8_t* mask, i
 }
 
 int nn_adam_step(float* param, const float* grad, float* m, float* v, uint16_t* param_bf16,
-                 int64_t n, float lr, float beta1, float beta2, float eps, int32_t t,
+                 int64_t n, double lr, double beta1, double beta2, double eps, int32_t t,
                  void* stream) {
-  if (!param || !grad || !m || !v || !param_bf16 || n < 1 || t < 1) {
+  if (!param || !grad || !m || !v || !param_bf16 || n < 1 || t < 1 || !(beta1 >= 0.0) ||
+      !(beta1 < 1.0) || !(beta2 >= 0.0) || !(beta2 < 1.0) || !(eps > 0.0)) {
     set_error("bad arguments");
     return -1;
   }
-  const float c1 = 1.f - powf(beta1, (float)t), c2 = 1.f - powf(beta2, (float)t);
+  // The complements 1 - beta and the bias corrections 1 - beta^t are
+  // formed in double: in float, 1 - 0.999f already carries a relative
+  // error of 1.3e-5 from the representation of beta2.
+  const double c1 = 1.0 - std::pow(beta1, (double)t), c2 = 1.0 - std::pow(beta2, (double)t);
   hipLaunchKernelGGL(k_adam, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, param, grad, m,
-                     v, param_bf16, n, lr, beta1, beta2, eps, c1, c2);
+                     v, param_bf16, n, (float)lr, (float)beta1, (float)(1.0 - beta1),
+                     (float)beta2, (float)(1.0 - beta2), (float)eps, (float)c1, (float)c2);
   NN_HIP_CHECK("adam");
   return 0;
 }

@@ -9,8 +9,8 @@ import ctypes
 from . import lbm
 
 NN_EXPORTED = ["nn_conv3d_fwd", "nn_conv3d_dgrad", "nn_conv3d_wgrad", "nn_conv3d_wgrad_workspace",
-               "nn_lrelu_bwd", "nn_up_concat", "nn_split_down", "nn_masked_mse", "nn_adam_step",
-               "nn_prepare_input", "nn_velocity_out", "nn_to_bf16"]
+               "nn_lrelu_bwd", "nn_up_concat", "nn_split_down", "nn_masked_mse",
+               "nn_adam_step", "nn_prepare_input", "nn_velocity_out", "nn_to_bf16"]
 
 
 class ConvDesc(ctypes.Structure):
@@ -32,6 +32,7 @@ def _lib():
         i64 = ctypes.c_int64
         i32 = ctypes.c_int32
         f32 = ctypes.c_float
+        f64 = ctypes.c_double
         sig = {
             "nn_conv3d_fwd": [D, vp, vp, vp, vp, vp],
             "nn_conv3d_dgrad": [D, vp, vp, vp, vp, i32, vp],
@@ -41,7 +42,7 @@ def _lib():
             "nn_up_concat": [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp],
             "nn_split_down": [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp],
             "nn_masked_mse": [vp, vp, vp, i64, vp, vp, vp, vp],
-            "nn_adam_step": [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp],
+            "nn_adam_step": [vp, vp, vp, vp, vp, i64, f64, f64, f64, f64, i32, vp],
             "nn_prepare_input": [vp, vp, i64, i32, vp],
             "nn_velocity_out": [vp, vp, ctypes.c_double, vp, i64, vp],
             "nn_to_bf16": [vp, vp, i64, vp],

@@ -55,11 +55,19 @@ def oracle_window_sample(mask, center, steps, f0_full=None, bounce="fullway", **
 
 
 def golden_duct130(name):
-    """Full 130 x 130 cross-section u_x[z][y] of a duct fixture in
-    tests/golden/ (stored as the quadrant y, z = 0..64; the duct is
-    mirror-symmetric in y and z)."""
+    """Full 130 x 130 cross-section u[3][z][y] of a duct fixture in
+    tests/golden/ (stored as u_x and u_y on the quadrant y, z = 0..64; the
+    square duct is mirror-symmetric in y and z, u_y odd in y, and the swap
+    y <-> z exchanges u_y and u_z)."""
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
     q = np.loadtxt(path)
-    top = np.concatenate([q, q[:, ::-1]], axis=1)
-    return np.concatenate([top, top[::-1, :]], axis=0)
+    h = q.shape[1]
+    qx, qy = q[:h], q[h:]
+
+    def unfold(quad, ysign):
+        top = np.concatenate([quad, ysign * quad[:, ::-1]], axis=1)
+        return np.concatenate([top, top[::-1, :]], axis=0)
+    ux = unfold(qx, 1.0)
+    uy = unfold(qy, -1.0)
+    return np.stack([ux, uy, uy.T])

@@ -59,7 +59,7 @@ def test_init_fields_is_the_oracle_equilibrium(L, kw):
     lat.init_fields(torch.from_numpy(rho).to(dev), torch.from_numpy(u.reshape(-1)).to(dev))
     got = lat.export()
     want = np.zeros((n, 19))
-    _, w, _ = O.table()
+    c, w, _ = O.table()
     solid = mask.reshape(-1) != 0
     for k in range(n):
         if solid[k]:
@@ -68,8 +68,14 @@ def test_init_fields_is_the_oracle_equilibrium(L, kw):
             want[k] = O.equilibrium(rho[k], u[:, k] - g / (2.0 * rho[k]))
     err = np.abs(got - want).max() / np.abs(want).max()
     assert err <= 1e-15, err
-    # the flow part is large enough that a wrong quadratic term would show
-    assert np.abs(want[~solid] - w).max() > 1e-2
+    # a wrong quadratic pair that keeps rho and j exact, 4 (c.u)^2 - 4/3 u^2
+    # in place of 9/2 (c.u)^2 - 3/2 u^2, moves the fluid populations by far
+    # more than the tolerance at these velocities
+    fl = ~solid
+    us = (u[:, fl] - g[:, None] / (2.0 * rho[fl])).T
+    cu = us @ c.T
+    wrong = w * rho[fl, None] * (1 + 3 * cu + 4 * cu ** 2 - (4.0 / 3.0) * (us ** 2).sum(1)[:, None])
+    assert np.abs(wrong - want[fl]).max() / np.abs(want).max() > 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -99,7 +105,6 @@ def test_verify_duct_matches_oracle_series(L, converged_ducts):
     quantities computed on the host from the exported velocity and the
     oracle's series (401 terms, the library's truncation).  The duct is not
     square, so swapped half-widths would show."""
-    import torch
     for (ny, nz), (lat, mask, g) in converged_ducts.items():
         nu = (0.8 - 0.5) / 3.0
         v = lat.verify(L.VERIFY_DUCT)
@@ -118,7 +123,6 @@ def test_verify_duct_matches_oracle_series(L, converged_ducts):
         # scheme at 14-28 nodes across) and is x-invariant
         assert v["rel_l2"] < 2e-2
         assert np.abs(u - u[:, :, :, :1]).max() <= 1e-15
-        del torch
 
 
 def test_verify_duct_second_order(L, converged_ducts):

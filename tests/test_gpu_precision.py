@@ -203,13 +203,12 @@ def test_full_size_shifted_channel_512(L, section512, mask512, layout, storage, 
 def _duct130_ref(name, nx, device):
     import torch
     from tests._util import golden_duct130
-    ux = golden_duct130(name)
-    ref = np.zeros((3, 130, 130, nx))
-    ref[0] = ux[:, :, None]
+    u = golden_duct130(name)
+    ref = np.ascontiguousarray(np.broadcast_to(u[:, :, :, None], (3, 130, 130, nx)))
     return torch.from_numpy(ref.reshape(-1)).to(device)
 
 
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-9), ("f32s", 1e-5), ("f16sr", 1e-3)])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-9), ("f32s", 1e-6), ("f16sr", 1e-3)])
 def test_midsize_duct_equal_step_error(L, storage, tol):
     """64 x 130 x 130 duct after exactly 20,000 updates against the oracle
     after the same number (tests/golden/duct130_step20000.txt): the
@@ -223,22 +222,39 @@ def test_midsize_duct_equal_step_error(L, storage, tol):
     assert v["rel_l2"] <= tol
 
 
-@pytest.mark.parametrize("storage,target,tol", [("f64", 1e-9, 1e-6), ("f32s", 1e-8, 1e-5),
-                                                ("f16sr", 1e-6, 1e-3)])
-def test_midsize_duct_steady_error(L, storage, target, tol):
-    """64 x 130 x 130 duct run to steady state against the converged oracle
-    (tests/golden/duct130_steady.txt, residual < 1e-10).  The slowest duct
-    mode decays over ~8,300 updates, so at a residual r per 100 updates
-    the remaining iteration error is ~83 r: FP64 and FP32 therefore run to
-    a tighter residual than 1e-6; the shifted storages may instead stop
-    at their residual plateau (FP16 with stochastic rounding: its storage
-    noise).  Half-way bounce-back, as in the fixture (the steady states of
-    the two bounce-back kinds agree; their transients do not)."""
+@pytest.fixture(scope="module")
+def duct130_f64_steps(L):
+    """Updates the FP64 64 x 130 x 130 duct needs to reach a velocity
+    residual of 1e-9 (its error against the converged oracle is then the
+    iteration error alone, ~1e-7)."""
+    mask = I.channel_mask(64, 130, 130)
+    lat = L.Lattice(mask, bounce="halfway", **PHYS)
+    steps, r, why = lat.run_to_steady(1e-9, max_steps=600000)
+    v = lat.verify(L.VERIFY_REFERENCE, _duct130_ref("duct130_steady.txt", 64, lat.device))
+    print("duct130 f64 steady: %d steps, residual %.2e (%s), u rel-L2 %.3e"
+          % (steps, r, why, v["rel_l2"]))
+    assert why == "converged"
+    assert v["rel_l2"] <= 1e-6
+    return steps
+
+
+@pytest.mark.parametrize("storage,tol", [("f32s", 1e-6), ("f16sr", 1e-3)])
+def test_midsize_duct_steady_error(L, duct130_f64_steps, storage, tol):
+    """64 x 130 x 130 duct: the shifted storages run the number of updates
+    the FP64 run needs to converge (residual 1e-9; ~135,000 updates, as the
+    slowest duct mode decays over ~8,300) and are compared with the
+    converged oracle (tests/golden/duct130_steady.txt).  This is the
+    equal-step form of the steady-state error: the storage's own residual
+    cannot serve as the stopping rule for FP16, whose rounding noise
+    (a residual floor near 2e-4) would stop it while a few 1e-3 of the
+    slowest mode are still left.  Half-way bounce-back, as in the fixture
+    (the steady states of the two bounce-back kinds agree; their
+    transients do not)."""
     mask = I.channel_mask(64, 130, 130)
     lat = L.Lattice(mask, storage=storage, bounce="halfway", **PHYS)
-    steps, r, why = lat.run_to_steady(target, max_steps=600000, plateau_checks=30)
+    lat.step(duct130_f64_steps)
     v = lat.verify(L.VERIFY_REFERENCE, _duct130_ref("duct130_steady.txt", 64, lat.device))
-    print("duct130 %s steady: %d steps, residual %.2e (%s), u rel-L2 %.3e"
-          % (storage, steps, r, why, v["rel_l2"]))
-    assert why in (("converged",) if storage == "f64" else ("converged", "plateau"))
+    r = lat.run_to_steady(0.0, max_steps=100)[1]
+    print("duct130 %s after %d updates: residual %.2e, u rel-L2 %.3e"
+          % (storage, duct130_f64_steps, r, v["rel_l2"]))
     assert v["rel_l2"] <= tol
