@@ -93,6 +93,18 @@ int nn_split_down(const float* dcat, float* dcoarse, float* dskip, int32_t batch
 int nn_masked_mse(const float* pred, const float* target, const uint8_t* mask, int64_t n,
                   uint16_t* dy, float* loss, float* workspace, void* stream);
 
+/* nn_masked_mse without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight training
+ * loops, harnesses that forbid hipMalloc): the same kernels and results
+ * bit for bit, on a 16 KiB device array inside the library (one per GPU,
+ * held until the process ends) instead of the caller's workspace.  It
+ * allocates nothing.  Call it with the stream's device current.
+ * n <= 2^31 - 1 voxels, else -1 with a message.  Every call on one GPU
+ * uses that GPU's array: calls that overlap on one GPU (concurrent
+ * streams or host threads) race, and the caller must order them. */
+int nn_masked_mse_noalloc(const float* pred, const float* target, const uint8_t* mask,
+                          int64_t n, uint16_t* dy, float* loss, void* stream);
+
 /* Adam step (Kingma and Ba) on float32 master weights; writes the bf16
  * copy used by the kernels.  t >= 1 is the step number.  The
  * hyper-parameters are double: the complements 1 - beta and the bias

@@ -10,6 +10,7 @@
 #include <stdint.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "../../include/lbm_nn.h"
 #include "internal.hpp"
@@ -1020,22 +1021,84 @@ int nn_split_down(const float* dcat, float* dcoarse, float* dskip, int32_t batch
   return 0;
 }
 
+// The three masked-MSE launches on a 4096-float workspace: per-block
+// partials (two floats for each of at most kMseMaxBlocks blocks), then the
+// fluid count at index 2 * kMseMaxBlocks + 1.  Every slot the final kernel
+// reads is written by the same call, so the workspace needs no clearing.
+constexpr int kMseMaxBlocks = 2046;
+constexpr int kMseWorkspace = 4096;
+static int masked_mse_launch(const float* pred, const float* target, const uint8_t* mask,
+                             int64_t n, uint16_t* dy, float* loss, float* workspace,
+                             hipStream_t s) {
+  int nb = (int)((n + 255) / 256);
+  if (nb > kMseMaxBlocks) nb = kMseMaxBlocks;
+  hipLaunchKernelGGL(k_mse_partial, dim3(nb), dim3(256), 0, s, pred, target, mask, n, workspace);
+  float* count = workspace + 2 * kMseMaxBlocks + 1;
+  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(256), 0, s, workspace, nb, loss, count);
+  hipLaunchKernelGGL(k_mse_grad, dim3(nblk(n * 16, 256)), dim3(256), 0, s, pred, target, mask, n,
+                     count, dy);
+  NN_HIP_CHECK("masked mse");
+  return 0;
+}
+
 int nn_masked_mse(const float* pred, const float* target, const uint8_t* mask, int64_t n,
                   uint16_t* dy, float* loss, float* workspace, void* stream) {
   if (!pred || !target || !mask || !dy || !loss || !workspace || n < 1) {
     set_error("bad arguments");
     return -1;
   }
-  hipStream_t s = (hipStream_t)stream;
-  int nb = (int)((n + 255) / 256);
-  if (nb > 2046) nb = 2046;
-  hipLaunchKernelGGL(k_mse_partial, dim3(nb), dim3(256), 0, s, pred, target, mask, n, workspace);
-  float* count = workspace + 2 * 2046 + 1;
-  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(256), 0, s, workspace, nb, loss, count);
-  hipLaunchKernelGGL(k_mse_grad, dim3(nblk(n * 16, 256)), dim3(256), 0, s, pred, target, mask, n,
-                     count, dy);
-  NN_HIP_CHECK("masked mse");
-  return 0;
+  return masked_mse_launch(pred, target, mask, n, dy, loss, workspace, (hipStream_t)stream);
+}
+
+// ---- allocation-free masked MSE ------------------------------------------
+// The workspace of nn_masked_mse_noalloc is this file-scope device array
+// (16 KiB; every GPU the library runs on holds its own copy until the
+// process ends).  Host code never uses the array's name as an address: the
+// device address is taken once per device with hipGetSymbolAddress, with
+// that device current, and kept in scratch_dev[].
+static __device__ __align__(256) float scratch[kMseWorkspace];
+
+constexpr int kMaxDevices = 64;
+constexpr int64_t kMseNoallocMaxVoxels = 0x7fffffffLL;
+static std::mutex scratch_mu;
+static float* scratch_dev[kMaxDevices] = {};
+
+static float* scratch_of_current_device() {
+  int dev = -1;
+  const hipError_t e0 = hipGetDevice(&dev);
+  if (e0 != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    set_error("nn_masked_mse_noalloc: no usable current device (%s, id %d)",
+              hipGetErrorString(e0), dev);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("nn_masked_mse_noalloc: hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                hipGetErrorString(e));
+      return nullptr;
+    }
+    scratch_dev[dev] = (float*)p;
+  }
+  return scratch_dev[dev];
+}
+
+int nn_masked_mse_noalloc(const float* pred, const float* target, const uint8_t* mask,
+                          int64_t n, uint16_t* dy, float* loss, void* stream) {
+  if (!pred || !target || !mask || !dy || !loss || n < 1) {
+    set_error("bad arguments");
+    return -1;
+  }
+  if (n > kMseNoallocMaxVoxels) {
+    set_error("nn_masked_mse_noalloc: %lld voxels exceed the maximum of %lld", (long long)n,
+              (long long)kMseNoallocMaxVoxels);
+    return -1;
+  }
+  float* ws = scratch_of_current_device();
+  if (!ws) return -4;
+  return masked_mse_launch(pred, target, mask, n, dy, loss, ws, (hipStream_t)stream);
 }
 
 int nn_adam_step(float* param, const float* grad, float* m, float* v, uint16_t* param_bf16,

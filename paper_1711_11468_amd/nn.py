@@ -10,7 +10,8 @@ from . import lbm
 
 NN_EXPORTED = ["nn_conv3d_fwd", "nn_conv3d_dgrad", "nn_conv3d_wgrad", "nn_conv3d_wgrad_workspace",
                "nn_lrelu_bwd", "nn_up_concat", "nn_split_down", "nn_masked_mse",
-               "nn_adam_step", "nn_prepare_input", "nn_velocity_out", "nn_to_bf16"]
+               "nn_masked_mse_noalloc", "nn_adam_step", "nn_prepare_input", "nn_velocity_out",
+               "nn_to_bf16"]
 
 
 class ConvDesc(ctypes.Structure):
@@ -42,6 +43,7 @@ def _lib():
             "nn_up_concat": [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp],
             "nn_split_down": [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp],
             "nn_masked_mse": [vp, vp, vp, i64, vp, vp, vp, vp],
+            "nn_masked_mse_noalloc": [vp, vp, vp, i64, vp, vp, vp],
             "nn_adam_step": [vp, vp, vp, vp, vp, i64, f64, f64, f64, f64, i32, vp],
             "nn_prepare_input": [vp, vp, i64, i32, vp],
             "nn_velocity_out": [vp, vp, ctypes.c_double, vp, i64, vp],
@@ -120,6 +122,14 @@ def split_down(dcat, dcoarse, dskip, batch, d, h, w, c1, c2, stream=None):
 def masked_mse(pred, target, mask, dy, loss, workspace, stream=None):
     _check(_lib().nn_masked_mse(_p(pred), _p(target), _p(mask), mask.numel(), _p(dy), _p(loss),
                                 _p(workspace), _s(stream)), "nn_masked_mse")
+
+
+def masked_mse_noalloc(pred, target, mask, dy, loss, stream=None, n=None):
+    """nn_masked_mse on the library's own device scratch (no workspace).
+    ``n``: voxel count (default: mask.numel())."""
+    _check(_lib().nn_masked_mse_noalloc(_p(pred), _p(target), _p(mask),
+                                        mask.numel() if n is None else int(n), _p(dy), _p(loss),
+                                        _s(stream)), "nn_masked_mse_noalloc")
 
 
 def adam_step(param, grad, m, v, param_bf16, lr, beta1, beta2, eps, t, stream=None):
