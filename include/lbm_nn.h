@@ -118,6 +118,24 @@ int nn_adam_step(float* param, const float* grad, float* m, float* v, uint16_t* 
  * (1/0), channel 1 = fluid (1/0), other channels zero. */
 int nn_prepare_input(const uint8_t* mask, uint16_t* x, int64_t n, int32_t c_pad, void* stream);
 
+/* Network input with distance features, for `batch` periodic cubes of
+ * edge n (mask and x voxel-major, x fastest): x[i][c_pad] bf16 with
+ * channel 0 = solid, 1 = fluid, 2 = d/dmax, 3 = (d/dmax)^2, other channels
+ * zero, where d is the distance to the nearest solid voxel (chamfer
+ * distance on the 26-neighbourhood with steps 1, sqrt 2, sqrt 3, periodic
+ * wrap), clamped at dmax.  In Stokes flow through a pore the velocity
+ * grows with the squared distance from the wall, which a few 3x3x3
+ * convolutions cannot measure across a pore.  work: 2*batch*n^3 floats.
+ * c_pad >= 4, 1 <= dmax <= 64, else -1. */
+int nn_prepare_input_dist(const uint8_t* mask, uint16_t* x, int32_t batch, int32_t n,
+                          int32_t c_pad, float dmax, float* work, void* stream);
+
+/* Network labels from solver velocities: out[i][a] = scale * u[a*n + i]
+ * on fluid voxels, 0 on solids (float32 [n][3]; u float64 [3][n]): the
+ * inverse of nn_velocity_out. */
+int nn_velocity_labels(const double* u, const uint8_t* mask, double scale, float* out, int64_t n,
+                       void* stream);
+
 /* Velocity for the solver: u[a*n + i] = scale * pred[i][a] on fluid
  * voxels, 0 on solids (float64, component-major [3][n]). */
 int nn_velocity_out(const float* pred, const uint8_t* mask, double scale, double* u, int64_t n,

@@ -682,6 +682,73 @@ __global__ void k_prepare_input(const uint8_t* __restrict__ mask, uint16_t* __re
   x[e] = f2bf(v);
 }
 
+// Distance to the nearest solid voxel: a chamfer distance on the
+// 26-neighbourhood (steps of 1, sqrt 2 and sqrt 3), on periodic cubes of
+// edge n, relaxed from 0 on solids and dmax on fluid; one sweep moves the
+// front by one voxel, so after ceil(dmax) sweeps every distance below dmax
+// has its final value.
+__global__ void k_dist_relax(const uint8_t* __restrict__ mask, const float* __restrict__ src,
+                             float* __restrict__ dst, int n, int64_t total, float dmax) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  if (mask[e] != 0) { dst[e] = 0.f; return; }
+  const int64_t n3 = (int64_t)n * n * n;
+  const int64_t base = e - e % n3;
+  const int r = (int)(e - base);
+  const int x = r % n, y = (r / n) % n, z = r / (n * n);
+  float best = src[e];
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int k = dx * dx + dy * dy + dz * dz;
+        if (k == 0) continue;
+        const float w = k == 1 ? 1.f : (k == 2 ? 1.41421356f : 1.73205081f);
+        int xx = x + dx, yy = y + dy, zz = z + dz;
+        xx = xx < 0 ? xx + n : (xx >= n ? xx - n : xx);
+        yy = yy < 0 ? yy + n : (yy >= n ? yy - n : yy);
+        zz = zz < 0 ? zz + n : (zz >= n ? zz - n : zz);
+        best = fminf(best, src[base + xx + (int64_t)n * (yy + (int64_t)n * zz)] + w);
+      }
+  dst[e] = fminf(best, dmax);
+}
+
+__global__ void k_dist_init(const uint8_t* __restrict__ mask, float* __restrict__ d, int64_t total,
+                            float dmax) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < total) d[e] = mask[e] != 0 ? 0.f : dmax;
+}
+
+// Input channels: 0 solid, 1 fluid, 2 d/dmax, 3 (d/dmax)^2, the rest zero.
+__global__ void k_features(const uint8_t* __restrict__ mask, const float* __restrict__ dist,
+                           uint16_t* __restrict__ x, int64_t total, int cpad, float dmax) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total * cpad) return;
+  const int64_t i = e / cpad;
+  const int c = (int)(e - i * cpad);
+  const bool solid = mask[i] != 0;
+  const float q = dist[i] / dmax;
+  float v = 0.f;
+  if (c == 0) v = solid ? 1.f : 0.f;
+  if (c == 1) v = solid ? 0.f : 1.f;
+  if (c == 2) v = q;
+  if (c == 3) v = q * q;
+  x[e] = f2bf(v);
+}
+
+// Network labels from solver velocities: out[i][a] = scale * u[a*n + i] on
+// fluid voxels, 0 on solids (the inverse of k_velocity_out).
+__global__ void k_velocity_labels(const double* __restrict__ u, const uint8_t* __restrict__ mask,
+                                  double scale, float* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool solid = mask[i] != 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) out[i * 3 + a] = solid ? 0.f : (float)(scale * u[a * n + i]);
+}
+
 __global__ void k_velocity_out(const float* __restrict__ pred, const uint8_t* __restrict__ mask,
                                double scale, double* __restrict__ u, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1129,6 +1196,41 @@ int nn_prepare_input(const uint8_t* mask, uint16_t* x, int64_t n, int32_t c_pad,
     hipLaunchKernelGGL(k_prepare_input<int64_t>, dim3(nblk((int64_t)n * c_pad, 256)), dim3(256), 0,
                        (hipStream_t)stream, mask, x, (int64_t)n, (int64_t)c_pad);
   NN_HIP_CHECK("prepare input");
+  return 0;
+}
+
+int nn_prepare_input_dist(const uint8_t* mask, uint16_t* x, int32_t batch, int32_t n,
+                          int32_t c_pad, float dmax, float* work, void* stream) {
+  if (!mask || !x || !work || batch < 1 || n < 1 || c_pad < 4 || !(dmax >= 1.f) ||
+      !(dmax <= 64.f)) {
+    set_error("bad arguments");
+    return -1;
+  }
+  const int64_t total = (int64_t)batch * n * n * n;
+  hipStream_t s = (hipStream_t)stream;
+  float* a = work;
+  float* b = work + total;
+  hipLaunchKernelGGL(k_dist_init, dim3(nblk(total, 256)), dim3(256), 0, s, mask, a, total, dmax);
+  const int sweeps = (int)ceilf(dmax);
+  for (int k = 0; k < sweeps; ++k) {
+    hipLaunchKernelGGL(k_dist_relax, dim3(nblk(total, 256)), dim3(256), 0, s, mask, a, b, n, total,
+                       dmax);
+    float* t = a;
+    a = b;
+    b = t;
+  }
+  hipLaunchKernelGGL(k_features, dim3(nblk(total * c_pad, 256)), dim3(256), 0, s, mask, a, x, total,
+                     c_pad, dmax);
+  NN_HIP_CHECK("prepare input with distance");
+  return 0;
+}
+
+int nn_velocity_labels(const double* u, const uint8_t* mask, double scale, float* out, int64_t n,
+                       void* stream) {
+  if (!u || !mask || !out || n < 1) { set_error("bad arguments"); return -1; }
+  hipLaunchKernelGGL(k_velocity_labels, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, u,
+                     mask, scale, out, n);
+  NN_HIP_CHECK("velocity labels");
   return 0;
 }
 

@@ -279,13 +279,31 @@ class Lattice:
                 "residual": st.residual, "nonfinite": st.nonfinite, "step": st.step, "rc": rc}
 
     def run_to_steady(self, tol: float, check_every: int = 100, max_steps: int = 1_000_000,
-                      plateau_checks: int = 0):
+                      plateau_checks: int = 0, confirm=(52, 120)):
         """Step until the velocity residual ||u^t - u^(t-check_every)|| / ||u^t||
-        (FP64, fluid nodes) falls below ``tol``.  With ``plateau_checks`` > 0,
-        also stop when the residual has not fallen below half of its earlier
-        minimum for that many consecutive checks (a precision floor).
-        Returns (steps, residual, reason) with reason in {"converged",
-        "plateau", "max_steps"}."""
+        (FP64, fluid nodes) falls below ``tol`` and then stays below it over
+        each further interval in ``confirm`` (update counts; () for no
+        confirmation).
+
+        An oscillation is invisible to a residual over k updates when its
+        period divides k.  On porous geometries the converged state of the
+        scheme is itself a limit cycle: bounce-back at staircase corners
+        leaves an exactly periodic component of period 2 (half-way) or 4
+        (full-way) that never decays (the oracle shows it too), so every
+        interval is a multiple of 4, or the cycle would read as unsteadiness
+        for ever.  Intervals 100, 52 and 120 (gcd 4) leave no other period
+        hidden from all three, e.g. an acoustic mode of the box whose period
+        divides 100; since a mode's swing over an interval also depends on
+        its phase, the intervals were chosen (by simulating the judge on
+        decaying sinusoids of every period from 10 to 300 updates and every
+        phase) so that no such mode passes with an amplitude above ~15 tol.
+        A failed confirmation continues the run (the next check spans
+        ``check_every`` updates from the last confirmation point).  With
+        ``plateau_checks`` > 0, also stop when the residual has not fallen
+        below half of its earlier minimum for that many consecutive checks
+        (a precision floor).  Returns (steps, residual, reason) with reason
+        in {"converged", "plateau", "max_steps"}; on convergence the
+        residual returned is the largest of the checks."""
         self.macroscopic()
         steps = 0
         best = float("inf")
@@ -295,7 +313,16 @@ class Lattice:
             self.step(check_every)
             steps += check_every
             r = self.macroscopic()["residual"]
-            if r < tol:
+            if r < tol and confirm:
+                for k in confirm:
+                    self.step(k)
+                    steps += k
+                    r = max(r, self.macroscopic()["residual"])
+                    if r >= tol:
+                        break
+                if r < tol:
+                    return steps, r, "converged"
+            elif r < tol:
                 return steps, r, "converged"
             if r < 0.5 * best:
                 best = r

@@ -10,7 +10,8 @@ from . import lbm
 
 NN_EXPORTED = ["nn_conv3d_fwd", "nn_conv3d_dgrad", "nn_conv3d_wgrad", "nn_conv3d_wgrad_workspace",
                "nn_lrelu_bwd", "nn_up_concat", "nn_split_down", "nn_masked_mse",
-               "nn_masked_mse_noalloc", "nn_adam_step", "nn_prepare_input", "nn_velocity_out",
+               "nn_masked_mse_noalloc", "nn_adam_step", "nn_prepare_input", "nn_prepare_input_dist",
+               "nn_velocity_labels", "nn_velocity_out",
                "nn_to_bf16"]
 
 
@@ -46,6 +47,8 @@ def _lib():
             "nn_masked_mse_noalloc": [vp, vp, vp, i64, vp, vp, vp],
             "nn_adam_step": [vp, vp, vp, vp, vp, i64, f64, f64, f64, f64, i32, vp],
             "nn_prepare_input": [vp, vp, i64, i32, vp],
+            "nn_prepare_input_dist": [vp, vp, i32, i32, i32, f32, vp, vp],
+            "nn_velocity_labels": [vp, vp, ctypes.c_double, vp, i64, vp],
             "nn_velocity_out": [vp, vp, ctypes.c_double, vp, i64, vp],
             "nn_to_bf16": [vp, vp, i64, vp],
         }
@@ -140,6 +143,17 @@ def adam_step(param, grad, m, v, param_bf16, lr, beta1, beta2, eps, t, stream=No
 def prepare_input(mask, x, c_pad, stream=None):
     _check(_lib().nn_prepare_input(_p(mask), _p(x), mask.numel(), c_pad, _s(stream)),
            "nn_prepare_input")
+
+
+def prepare_input_dist(mask, x, batch, n, c_pad, dmax, work, stream=None):
+    _check(_lib().nn_prepare_input_dist(_p(mask), _p(x), int(batch), int(n), int(c_pad),
+                                        float(dmax), _p(work), _s(stream)),
+           "nn_prepare_input_dist")
+
+
+def velocity_labels(u, mask, scale, out, stream=None):
+    _check(_lib().nn_velocity_labels(_p(u), _p(mask), float(scale), _p(out), mask.numel(),
+                                     _s(stream)), "nn_velocity_labels")
 
 
 def velocity_out(pred, mask, scale, u, stream=None):

@@ -6,7 +6,7 @@ compare warm and cold starts on held-out geometries.
 
 Training data: seeds 0 .. train-1 at edge n (porosity uniform in
 [0.35, 0.70], sphere radii in [4, 8]), each solved by the FP64 list sweep to
-residual 1e-6; labels are u * nu / g divided by their RMS over fluid voxels.
+residual 1e-6; labels are u * nu / (g * kc_scale(porosity)).
 Evaluation: seeds 100000 .. 100000+eval-1 at edge eval-n; each geometry is
 solved from rest and from the network's prediction (inference included in
 the warm time); both runs stop at residual 1e-6.
@@ -29,7 +29,7 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=4)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--eval", type=int, default=20)
     ap.add_argument("--eval-n", type=int, default=128)
     ap.add_argument("--out", default="unet_porous.npz")
@@ -48,17 +48,13 @@ def main(argv=None):
         net = UNet.load(args.load)
     else:
         t0 = time.perf_counter()
-        masks, labels, info = WS.make_dataset(list(range(args.train)), args.n, u_scale=1.0,
+        masks, labels, info = WS.make_dataset(list(range(args.train)), args.n,
                                               workers=args.workers, log=log)
         t_data = time.perf_counter() - t0
-        fl = masks == 0
-        lab = labels.view(args.train, -1, 3)
-        u_scale = float(lab[fl].pow(2).mean().sqrt())
-        labels /= u_scale
         steps = [r["steps"] for r in info]
-        log("dataset: %d geometries in %.1f s, solver steps median %d (max %d), label rms %.4f"
-            % (args.train, t_data, int(np.median(steps)), max(steps), u_scale))
-        net = UNet(seed=0, u_scale=u_scale)
+        log("dataset: %d geometries in %.1f s, solver steps median %d (max %d)"
+            % (args.train, t_data, int(np.median(steps)), max(steps)))
+        net = UNet(seed=0)
         t0 = time.perf_counter()
         hist = WS.train(net, masks, labels, args.n, args.epochs, args.batch, args.lr, log=log)
         torch.cuda.synchronize()
@@ -66,7 +62,7 @@ def main(argv=None):
         net.save(args.out)
         log("trained %d epochs in %.1f s, saved %s" % (args.epochs, t_train, args.out))
         summary.update({"dataset_seconds": t_data, "train_seconds": t_train, "loss_history": hist,
-                        "u_scale": u_scale, "dataset_steps_median": float(np.median(steps))})
+                        "dataset_steps_median": float(np.median(steps))})
         del masks, labels
         torch.cuda.empty_cache()
     rows = []

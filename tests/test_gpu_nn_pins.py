@@ -112,3 +112,61 @@ def test_velocity_out_definition(NN):
     want = scale * pred.astype(np.float64).T.copy()
     want[:, mask != 0] = 0.0
     assert np.array_equal(u.cpu().numpy().reshape(3, n), want)
+
+
+def test_distance_features_closed_form(NN):
+    """nn_prepare_input_dist around a single solid voxel of a periodic cube:
+    the 26-neighbourhood chamfer distance to it has the closed form
+    (a - b) + (b - c) sqrt 2 + c sqrt 3 for sorted offsets a >= b >= c
+    (minimum image), clamped at dmax; channels 2 and 3 carry d/dmax and
+    (d/dmax)^2 rounded to bf16 (within one bf16 ulp of the float64 value,
+    since the kernel sums the steps in float32), channels 0/1 the solid and
+    fluid indicators, the padding channels zero.  Two cubes in one batch,
+    the solid voxel at different places (the batch index does not leak)."""
+    dev = torch.device("cuda")
+    n, dmax, cpad = 16, 6.0, 16
+    mask = np.zeros((2, n, n, n), np.uint8)       # [b][z][y][x]
+    spots = [(3, 5, 7), (12, 0, 15)]              # (x, y, z)
+    for b, (x, y, z) in enumerate(spots):
+        mask[b, z, y, x] = 1
+    x_t = torch.empty(2 * n ** 3 * cpad, dtype=torch.bfloat16, device=dev)
+    work = torch.empty(2 * 2 * n ** 3, dtype=torch.float32, device=dev)
+    NN.prepare_input_dist(torch.from_numpy(mask.reshape(-1)).to(dev), x_t, 2, n, cpad, dmax, work)
+    got = x_t.float().cpu().numpy().reshape(2, n, n, n, cpad)
+    zz, yy, xx = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    for b, (x0, y0, z0) in enumerate(spots):
+        off = [np.minimum(np.abs(v - v0), n - np.abs(v - v0)) for v, v0 in ((xx, x0), (yy, y0), (zz, z0))]
+        srt = np.sort(np.stack(off), axis=0)[::-1]
+        a, bb, c = srt[0], srt[1], srt[2]
+        d = np.minimum((a - bb) + (bb - c) * np.sqrt(2.0) + c * np.sqrt(3.0), dmax)
+        q = d / dmax
+        solid = mask[b] != 0
+        assert np.array_equal(got[b, ..., 0], solid.astype(np.float32))
+        assert np.array_equal(got[b, ..., 1], (~solid).astype(np.float32))
+        for ch, want in ((2, q), (3, q * q)):
+            assert np.all(np.abs(got[b, ..., ch] - want) <= 2.0 ** -8 * np.abs(want) + 1e-30), ch
+        assert np.all(got[b, ..., 4:] == 0)
+    # the clamp is reached somewhere and the distances are not all equal
+    assert got[0, ..., 2].max() == 1.0 and got[0, ..., 2][mask[0] == 0].min() == pytest.approx(1 / dmax, rel=1e-2)
+
+
+def test_velocity_labels_inverse_of_velocity_out(NN):
+    """nn_velocity_labels(u, mask, s) = s * u transposed to [n][3] in
+    float32 (round to nearest), 0 on solids; fed back through
+    nn_velocity_out with scale 1/s it returns u to float32 precision."""
+    dev = torch.device("cuda")
+    n = 9999
+    rng = np.random.default_rng(6)
+    u = rng.normal(size=(3, n)) * 1e-3
+    mask = (rng.uniform(size=n) < 0.4).astype(np.uint8)
+    u[:, mask != 0] = 0.0
+    scale = 1.0 / (1e-6 / 0.1 * 0.37)
+    out = torch.full((n * 3,), np.nan, dtype=torch.float32, device=dev)
+    m_t = torch.from_numpy(mask).to(dev)
+    NN.velocity_labels(torch.from_numpy(u.reshape(-1)).to(dev), m_t, scale, out)
+    want = (scale * u).T.astype(np.float32)
+    want[mask != 0] = 0.0
+    assert np.array_equal(out.cpu().numpy().reshape(n, 3), want)
+    back = torch.empty(3 * n, dtype=torch.float64, device=dev)
+    NN.velocity_out(out, m_t, 1.0 / scale, back)
+    assert np.allclose(back.cpu().numpy().reshape(3, n), u, rtol=2 ** -23, atol=0)

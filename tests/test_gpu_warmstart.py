@@ -1,8 +1,10 @@
 """The learned warm start end to end on held-out porous boxes, with the
 network trained by the library's own kernels (weights committed with the
-package): the prediction beats the zero guess, both starts converge, and the
-warm-versus-cold gain is measured.  A warm start from the exact steady field
-shows the gain an accurate prediction buys."""
+package): the prediction is accurate to the stated level, both starts
+converge to the same field (the solver stays the judge), and the warm start
+reaches the residual target in fewer updates and less wall time, inference
+included.  A warm start from the exact steady field shows the gain an
+accurate prediction buys."""
 import os
 
 import numpy as np
@@ -23,17 +25,53 @@ def WS():
     return warmstart
 
 
-def test_trained_network_on_held_out_geometries(WS):
+@pytest.fixture(scope="module")
+def held_out(WS):
+    """Cold versus warm on three held-out 128^3 boxes (seeds 100000..2,
+    porosity drawn from [0.35, 0.70]; the network was trained on 64^3)."""
     from paper_1711_11468_amd.surrogate import UNet
     net = UNet.load(WEIGHTS)
-    rows = [WS.compare(net, 100000 + k, 64) for k in range(2)]
+    rows = [WS.compare(net, 100000 + k, 128) for k in range(3)]
     for r in rows:
         print(r)
+    return rows
+
+
+def test_held_out_both_starts_converge_to_one_field(held_out):
+    """Both runs meet the judge, and their converged fields, averaged over
+    4 updates so that the corner limit cycle cancels, agree far below the
+    residual target: the warm start settles on the same steady state (the
+    instantaneous fields differ by the cycle, ~1e-3, whose amplitude
+    depends on the start)."""
+    for r in held_out:
         assert r["cold_reason"] == "converged" and r["warm_reason"] == "converged"
-        assert r["prediction_rel_l2"] < 0.9          # better than the zero guess (1.0)
-        assert r["warm_vs_cold_rel_l2"] < 5e-2
-    gain = np.median([r["cold_steps"] / r["warm_steps"] for r in rows])
-    print("median step gain of the trained network: %.2f" % gain)
+        assert r["warm_vs_cold_rel_l2"] < 1e-5, r
+
+
+def test_held_out_prediction_error(held_out):
+    """Relative L2 error of the predicted velocity against the cold-start
+    steady field on the 128^3 boxes (trained on 64^3): median at most 0.3
+    (measured 0.22 over twenty boxes; 0.09-0.12 on held-out 64^3 boxes;
+    the zero guess scores 1)."""
+    errs = [r["prediction_rel_l2"] for r in held_out]
+    print("prediction errors", errs)
+    assert np.median(errs) <= 0.3
+
+
+@pytest.mark.xfail(reason="the learned warm start is slower than the cold start: median 0.38x "
+                          "in steps and wall time over twenty held-out 128^3 boxes.  Any "
+                          "voxel-scale velocity error of ~10% (network error, or plain noise on "
+                          "the exact field) excites slowly decaying near-wall modes that cost "
+                          "2-4x the cold steps; only a near-exact field gains (exact velocity: "
+                          "1.4-2.3x)", strict=False)
+def test_held_out_warm_start_gain(held_out):
+    """Median over the held-out boxes: fewer updates and less wall time
+    (inference included) to the residual target than the cold start."""
+    steps = np.median([r["cold_steps"] / r["warm_steps"] for r in held_out])
+    wall = np.median([r["cold_s"] / r["warm_s"] for r in held_out])
+    print("median gain: steps %.3f, wall time %.3f" % (steps, wall))
+    assert steps > 1.0
+    assert wall > 1.0
 
 
 def test_exact_field_warm_start_gain(WS):
@@ -45,11 +83,9 @@ def test_exact_field_warm_start_gain(WS):
     lat, steps_c, _, _, _ = WS.solve(mask)
     ref = lbm.Lattice(mask, addressing="list", bounce="halfway", **WS.PHYS)
     ref.run_to_steady(1e-11, max_steps=100000)
-    u_ref = ref.macroscopic(fields=True)["u"].clone()
+    u_ref = ref.macroscopic(fields=True)["u"].reshape(-1).clone()
     lat_w, steps_w, _, _, why = WS.solve(mask, u0=u_ref)
-    fl = torch.from_numpy(mask.reshape(-1) == 0).to(u_ref.device)
-    u_w = lat_w.macroscopic(fields=True)["u"]
-    err = float(((u_w - u_ref)[:, fl].norm() / u_ref[:, fl].norm()).item())
+    err = lat_w.verify(lbm.VERIFY_REFERENCE, u_ref)["rel_l2"]
     print("cold", steps_c, "exact-warm", steps_w, "err", err)
     assert why == "converged"
     assert steps_w * 1.2 <= steps_c
