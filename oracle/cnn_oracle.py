@@ -4,7 +4,9 @@ Plain PyTorch CPU operations in float64: ``conv3d`` on circularly padded
 input, leaky ReLU, nearest-neighbour upsampling, concatenation, masked mean
 squared error, with gradients from autograd; the Adam update written out
 from its definition (Kingma and Ba, "Adam: A Method for Stochastic
-Optimization", 2015, Algorithm 1) in float64 numpy.  It shares no code with the
+Optimization", 2015, Algorithm 1) in float64 numpy; the network's distance
+input features from a library shortest-path routine (scipy's Dijkstra) on
+the voxel graph.  It shares no code with the
 GPU kernels; it takes the same weights (rounded to bf16 by the caller when
 comparing with the bf16 kernels) in the layout [taps][c_out][c_in] and
 channels-last activations [B][D][H][W][C].
@@ -95,3 +97,59 @@ def bf16_bits_rne(x):
     b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
     rounded = (b + 0x7FFF + ((b >> 16) & 1)) >> 16
     return rounded.astype(np.uint16)
+
+
+def chamfer_distance(solid, dmax):
+    """Distance of every voxel of the periodic boxes ``solid`` (bool
+    [B][D][H][W]) to the nearest solid voxel along paths of the
+    26-neighbourhood with step lengths 1, sqrt 2 and sqrt 3 (the 3-D
+    chamfer metric of Borgefors, "Distance transformations in digital
+    images", 1986, with exact step lengths), clamped at dmax.  Computed as
+    shortest paths from a virtual source joined to every solid voxel
+    (scipy.sparse.csgraph.dijkstra), float64 [B][D][H][W]."""
+    import numpy as np
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import dijkstra
+    solid = np.asarray(solid, dtype=bool)
+    out = np.empty(solid.shape)
+    for b in range(solid.shape[0]):
+        D, H, W = solid[b].shape
+        n = D * H * W
+        z, y, x = np.meshgrid(np.arange(D), np.arange(H), np.arange(W), indexing="ij")
+        idx = (z * H + y) * W + x
+        rows, cols, vals = [], [], []
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    k = dz * dz + dy * dy + dx * dx
+                    if k == 0:
+                        continue
+                    nb = (((z + dz) % D) * H + (y + dy) % H) * W + (x + dx) % W
+                    rows.append(idx.ravel())
+                    cols.append(nb.ravel())
+                    vals.append(np.full(n, np.sqrt(k)))
+        src = np.flatnonzero(solid[b].ravel())
+        rows.append(np.full(src.size, n))
+        cols.append(src)
+        vals.append(np.full(src.size, 1e-300))  # virtual source, zero length in effect
+        g = coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                       shape=(n + 1, n + 1)).tocsr()
+        d = dijkstra(g, directed=True, indices=n)[:n]
+        d[solid[b].ravel()] = 0.0  # (the virtual edges carry a tiny length,
+        #                             since the graph routine drops zero ones)
+        out[b] = np.minimum(d, dmax).reshape(D, H, W)
+    return out
+
+
+def input_features(solid, dmax=12.0):
+    """Network input [B][D][H][W][16] float64: solid and fluid indicators,
+    d/dmax and (d/dmax)^2 with d = chamfer_distance(solid, dmax), zeros."""
+    import numpy as np
+    solid = np.asarray(solid, dtype=bool)
+    q = chamfer_distance(solid, dmax) / dmax
+    x = np.zeros(solid.shape + (16,))
+    x[..., 0] = solid
+    x[..., 1] = ~solid
+    x[..., 2] = q
+    x[..., 3] = q * q
+    return torch.from_numpy(x)

@@ -55,13 +55,22 @@ struct StoreF64 {
 // double -> float with stochastic rounding: a uniform 29-bit random value
 // is added to the magnitude below the last float mantissa bit and the sum
 // is truncated, so a value rounds up with probability equal to its fraction
-// of a float ulp and the expected stored value equals the input.
+// of a float ulp and the expected stored value equals the input.  The
+// truncation is done on the bit fields (a few integer operations; the
+// library's round-toward-zero conversion expands to compare-and-select
+// sequences that tripled the sweep's instruction count).  Magnitudes below
+// the float normal range (2^-126) are flushed to zero and those beyond it
+// saturate to infinity; the populations stored here lie far inside it.
 __device__ __forceinline__ float sr_f64_to_f32(double v, uint32_t rnd) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned long long sign = b & 0x8000000000000000ull;
-  const unsigned long long mag = (b ^ sign) + (unsigned long long)(rnd >> 3);
-  const float r = __double2float_rz(__longlong_as_double((long long)mag));
-  return sign ? -r : r;
+  const uint32_t sign = (uint32_t)(b >> 32) & 0x80000000u;
+  const unsigned long long mag = (b & 0x7fffffffffffffffull) + (unsigned long long)(rnd >> 3);
+  const int e = (int)(mag >> 52) - (1023 - 127);  // float biased exponent
+  uint32_t fb;
+  if (e <= 0) fb = 0u;
+  else if (e >= 255) fb = 0x7f800000u;
+  else fb = ((uint32_t)e << 23) | ((uint32_t)(mag >> 29) & 0x7fffffu);
+  return __uint_as_float(fb | sign);
 }
 
 // Float storage of h = f - w.  The collision runs in double and each stored
@@ -148,9 +157,60 @@ struct Collide {
   uint32_t step;       // time step being computed (stochastic rounding key)
 };
 
-// In-place TRT collision of one fluid node.  SHIFTED: f holds h = f - w.
+// The collision in double arithmetic (FP64 storage, and FP32 storage, whose
+// collision runs in double): the textbook form, with u = J / rho.  Its
+// register footprint keeps the FP64 sweep free of scratch spills.
 template <typename R, bool SHIFTED>
-__device__ __forceinline__ void trt_collide(R (&f)[Q], const Collide<R>& k) {
+__device__ __forceinline__ void trt_collide_double(R (&f)[Q], const Collide<R>& k) {
+  R s = f[0];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) s += f[i];
+  const R rho = SHIFTED ? R(1) + s : s;
+  R jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+  for (int i = 1; i < Q; i += 2) {
+    const R d = f[i] - f[i + 1];
+    if (Vel::cx[i] != 0) jx += Vel::cx[i] > 0 ? d : -d;
+    if (Vel::cy[i] != 0) jy += Vel::cy[i] > 0 ? d : -d;
+    if (Vel::cz[i] != 0) jz += Vel::cz[i] > 0 ? d : -d;
+  }
+  const R inv_rho = R(1) / rho;
+  const R ux = (jx + R(0.5) * k.gx) * inv_rho;
+  const R uy = (jy + R(0.5) * k.gy) * inv_rho;
+  const R uz = (jz + R(0.5) * k.gz) * inv_rho;
+  const R usq = ux * ux + uy * uy + uz * uz;
+  const R ug = ux * k.gx + uy * k.gy + uz * k.gz;
+  // e_i - (SHIFTED ? w_i : 0) = w_i (s + rho (3 cu + 9/2 cu^2 - 3/2 usq))
+  {
+    const R w = R(weight(0));
+    const R e0 = w * (s - R(1.5) * rho * usq);
+    const R F0 = w * (R(-3) * ug);
+    f[0] = f[0] + k.lp * (e0 - f[0]) + k.ap * F0;
+  }
+#pragma unroll
+  for (int i = 1; i < Q; i += 2) {
+    const R w = R(weight(i));
+    const R cu = R(Vel::cx[i]) * ux + R(Vel::cy[i]) * uy + R(Vel::cz[i]) * uz;
+    const R cg = R(Vel::cx[i]) * k.gx + R(Vel::cy[i]) * k.gy + R(Vel::cz[i]) * k.gz;
+    const R ep = w * (s + rho * (R(4.5) * cu * cu - R(1.5) * usq));
+    const R em = w * (R(3) * rho * cu);
+    const R Fp = w * (R(9) * cu * cg - R(3) * ug);
+    const R Fm = w * (R(3) * cg);
+    const R fp = R(0.5) * (f[i] + f[i + 1]);
+    const R fm = R(0.5) * (f[i] - f[i + 1]);
+    const R sym = k.lp * (ep - fp) + k.ap * Fp;
+    const R asym = k.lm * (em - fm) + k.am * Fm;
+    f[i] = f[i] + sym + asym;
+    f[i + 1] = f[i + 1] + sym - asym;
+  }
+}
+
+// The collision in float arithmetic (FP16 storage): the equilibrium's odd
+// part is formed from J = rho u directly and the constant 3 w_i is a float
+// pair hi + lo (see below), which removes the systematic momentum gain the
+// rounding of the float weights would leave.
+template <typename R, bool SHIFTED>
+__device__ __forceinline__ void trt_collide_float(R (&f)[Q], const Collide<R>& k) {
   R s = f[0];
 #pragma unroll
   for (int i = 1; i < Q; ++i) s += f[i];
@@ -193,14 +253,9 @@ __device__ __forceinline__ void trt_collide(R (&f)[Q], const Collide<R>& k) {
     // updates a duct takes to develop, outgrows the storage rounding
     // (1e-4 of the velocity on a 130 x 130 duct).  The constant 3 w_i is
     // therefore split into a float pair hi + lo, exact to ~1e-15.
-    R em;
-    if constexpr (std::is_same<R, float>::value) {
-      const float w3hi = (float)(3.0 * weight(i));
-      const float w3lo = (float)(3.0 * weight(i) - (double)w3hi);
-      em = w3hi * cJ + w3lo * cJ;
-    } else {
-      em = w * (R(3) * cJ);
-    }
+    const R w3hi = (R)(3.0 * weight(i));
+    const R w3lo = (R)(3.0 * weight(i) - (double)w3hi);
+    const R em = w3hi * cJ + w3lo * cJ;
     const R Fp = w * (R(9) * cu * cg - R(3) * ug);
     const R Fm = w * (R(3) * cg);
     const R fp = R(0.5) * (f[i] + f[i + 1]);
@@ -210,6 +265,15 @@ __device__ __forceinline__ void trt_collide(R (&f)[Q], const Collide<R>& k) {
     f[i] = f[i] + sym + asym;
     f[i + 1] = f[i + 1] + sym - asym;
   }
+}
+
+// In-place TRT collision of one fluid node.  SHIFTED: f holds h = f - w.
+template <typename R, bool SHIFTED>
+__device__ __forceinline__ void trt_collide(R (&f)[Q], const Collide<R>& k) {
+  if constexpr (std::is_same<R, float>::value)
+    trt_collide_float<R, SHIFTED>(f, k);
+  else
+    trt_collide_double<R, SHIFTED>(f, k);
 }
 
 // Density and velocity of a (pre-collision, unshifted) node in double.

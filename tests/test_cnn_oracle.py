@@ -135,3 +135,32 @@ def test_bf16_rounding_bits():
     # ties go to even: 1 + 2^-8 lies halfway between 1 and 1 + 2^-7
     assert R.bf16_bits_rne(np.float32(1.0 + 2 ** -8)) == 0x3F80
     assert R.bf16_bits_rne(np.float32(1.0 + 3 * 2 ** -8)) == 0x3F82
+
+
+def test_chamfer_distance_brute_force():
+    """The reference distance features: for the 26-neighbourhood with step
+    lengths 1, sqrt 2, sqrt 3 the shortest path between two voxels with
+    sorted offsets a >= b >= c is (a - b) + (b - c) sqrt 2 + c sqrt 3, so
+    the distance to the nearest solid is the minimum of that closed form
+    over the solid voxels (periodic minimum image): brute force on small
+    random boxes, and the clamp."""
+    import numpy as np
+    rng = np.random.default_rng(9)
+    solid = rng.uniform(size=(2, 6, 7, 5)) < 0.08
+    solid[1, 0, 0, 0] = True
+    got = R.chamfer_distance(solid, 100.0)
+    for b in range(2):
+        D, H, W = solid[b].shape
+        pts = np.argwhere(solid[b])
+        for z in range(D):
+            for y in range(H):
+                for x in range(W):
+                    best = np.inf
+                    for (pz, py, px) in pts:
+                        off = sorted([min(abs(x - px), W - abs(x - px)), min(abs(y - py), H - abs(y - py)),
+                                      min(abs(z - pz), D - abs(z - pz))], reverse=True)
+                        a, bb, c = off
+                        best = min(best, (a - bb) + (bb - c) * np.sqrt(2) + c * np.sqrt(3))
+                    assert abs(got[b, z, y, x] - best) <= 1e-12
+    clamped = R.chamfer_distance(solid, 1.5)
+    assert clamped.max() == 1.5 and np.all(clamped[solid] == 0)

@@ -104,9 +104,8 @@ def test_unet_forward_backward_vs_reference(NN):
     torch.cuda.synchronize()
     params = {k: (R.bf16_round(v["w"].cpu().double()).requires_grad_(),
                   v["b"].cpu().double().requires_grad_()) for k, v in net.p.items()}
-    x = torch.zeros(B, n, n, n, 16, dtype=torch.float64)
-    x[..., 0] = solid.double()
-    x[..., 1] = (~solid).double()
+    from paper_1711_11468_amd.surrogate import DMAX
+    x = R.bf16_round(R.input_features(solid.numpy(), DMAX))   # the kernel stores bf16
     ref = R.unet(x, params)
     L = R.masked_mse(ref, tgt.double(), ~solid)
     L.backward()
