@@ -122,7 +122,8 @@ typedef struct {
   int32_t f16_scale_log2;   /* s for the F16 storages, 0..24; else ignored */
   int32_t block;            /* threads per workgroup, 0 = default; a
                                multiple of 64 up to 1024 (the AA kernels
-                               take at most 512 and cut larger values; the
+                               and the FP32-storage SoA pull take at most
+                               512 and cut larger values; the
                                AoS column marches - pull, push, AA
                                neighbour step - run their own shapes)      */
   int32_t pad;              /* extra elements between direction arrays

@@ -48,6 +48,7 @@ struct StoreF64 {
   using R = double;
   static constexpr bool kShifted = false;
   static constexpr bool kStochastic = false;
+  static constexpr int kRowBlockMax = 1024;  // largest row workgroup of the SoA pull
   __device__ __forceinline__ static R load(T v, R) { return v; }
   __device__ __forceinline__ static T store(R v, R, uint32_t) { return v; }
 };
@@ -85,6 +86,9 @@ struct StoreF32Shifted {
   using R = double;
   static constexpr bool kShifted = true;
   static constexpr bool kStochastic = true;
+  // The double collision needs more than the 128 registers a 1024-thread
+  // bound leaves; with 512-thread rows it runs without spilling.
+  static constexpr int kRowBlockMax = 512;
   __device__ __forceinline__ static R load(T v, R) { return (R)v; }
   // rnd: a random word whose top 29 bits are uniformly distributed
   __device__ __forceinline__ static T store(R v, R, uint32_t rnd) { return sr_f64_to_f32(v, rnd); }
@@ -95,6 +99,7 @@ struct StoreF16Shifted {
   using R = float;
   static constexpr bool kShifted = true;
   static constexpr bool kStochastic = false;
+  static constexpr int kRowBlockMax = 1024;  // largest row workgroup of the SoA pull
   // scale = 2^s on store, 2^-s on load: exact (power of two), so the only
   // rounding is the float -> half conversion (round to nearest even).
   __device__ __forceinline__ static R load(T v, R inv_scale) { return (R)v * inv_scale; }
@@ -123,6 +128,7 @@ struct StoreF16ShiftedSR {
   using R = float;
   static constexpr bool kShifted = true;
   static constexpr bool kStochastic = true;
+  static constexpr int kRowBlockMax = 1024;  // largest row workgroup of the SoA pull
   __device__ __forceinline__ static R load(T v, R inv_scale) { return (R)v * inv_scale; }
   // rnd: a random word whose top 13 bits are uniformly distributed
   __device__ __forceinline__ static T store(R v, R scale, uint32_t rnd) {

@@ -23,7 +23,7 @@
 namespace lbm {
 
 template <class ST, int BB>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(ST::kRowBlockMax)
 k_sweep_soa(const typename ST::T* __restrict__ src, typename ST::T* __restrict__ dst,
             const uint8_t* __restrict__ mask, const uint32_t* __restrict__ links, int nx,
             int ny, int nz, int64_t stride, Collide<typename ST::R> k) {
@@ -172,7 +172,9 @@ hipError_t launch_pull(lbm_ctx* c, const void* src, void* dst) {
                          s, d, c->b.adj, nf, c->s.stride, k);
       return hipGetLastError();
     }
-    const dim3 grid((unsigned)p.ny * (unsigned)p.nz), block(row_block(c));
+    int blk = row_block(c);
+    if (blk > ST::kRowBlockMax) blk = ST::kRowBlockMax;
+    const dim3 grid((unsigned)p.ny * (unsigned)p.nz), block(blk);
     if (p.bounce == LBM_FULLWAY)
       hipLaunchKernelGGL((k_sweep_soa<ST, LBM_FULLWAY>), grid, block, lds, c->stream, s, d,
                          c->b.mask, c->b.links, p.nx, p.ny, p.nz, c->s.stride, k);

@@ -1,0 +1,171 @@
+"""Why the learned warm start does not pay: updates to the steady-state
+judge's target from starts of controlled error structure, on held-out
+porous boxes (FP64 list form, half-way bounce-back, the warm-start physics).
+
+Starts: rest (cold); the exact steady velocity (from a run converged to a
+residual of 1e-12) with rho = 1 and with the exact density; 0.8 x the exact
+velocity (a pure, smooth scale error); the exact velocity plus 10% (of the
+velocity RMS) of voxel noise on the interior only or on the wall layer only
+(fluid nodes with a solid face neighbour), or smoothed over ~3 voxels; the
+network's prediction as is and with its wall layer replaced by the exact
+one; and the cold start with its flow part rescaled, after T0 updates, to
+the predicted or the exact final mean flux.  Each run reports its update
+count and its 4-update-mean distance to the exact field.
+
+    python -m paper_1711_11468_amd.warmstart_study [--sizes 64,128] \\
+        [--seeds 100000,100001] [--out study.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+import numpy as np
+
+from . import lbm
+from . import warmstart as WS
+
+
+def _lattice(mask):
+    return lbm.Lattice(mask, addressing="list", bounce="halfway", **WS.PHYS)
+
+
+def _run(mask, u_ref_mean, u0=None, rho0=None, lat=None):
+    import torch
+    if lat is None:
+        lat = _lattice(mask)
+        if u0 is not None or rho0 is not None:
+            lat.init_fields(rho0, u0)
+    steps, r, why = lat.run_to_steady(WS.TOL, max_steps=100000)
+    um = WS.cycle_mean_velocity(lat)
+    fl = torch.from_numpy(mask.reshape(-1) == 0).to(um.device).repeat(3)
+    err = float(((um - u_ref_mean)[fl].norm() / u_ref_mean[fl].norm()).item())
+    return {"steps": int(steps), "reason": why, "end_rel_l2": err}
+
+
+def _smooth(noise, fluid3, n, passes=4):
+    """Masked neighbour averaging of a [3][n^3] field (fluid nodes only)."""
+    import torch
+    fl = fluid3[0].view(n, n, n).double()
+    u = noise.view(3, n, n, n) * fl
+    for _ in range(passes):
+        acc = u.clone()
+        cnt = fl.clone()
+        for d in range(3):
+            for s in (-1, 1):
+                acc += torch.roll(u, s, dims=d + 1)
+                cnt += torch.roll(fl, s, dims=d)
+        u = acc / cnt.clamp(min=1) * fl
+    return u.reshape(-1)
+
+
+def study_box(net, n, seed, rng_seed=0):
+    import torch
+    from scipy import ndimage
+    mask, phi = WS.geometry(seed, n)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    ref = _lattice(mask)
+    ref.run_to_steady(1e-12, max_steps=200000)
+    st = ref.macroscopic(fields=True)
+    u_ref = st["u"].reshape(-1).clone()
+    rho_ref = st["rho"].clone()
+    true_flux = ref.macroscopic()["momentum"][0]
+    u_ref_mean = WS.cycle_mean_velocity(ref)
+    del ref
+    m = torch.from_numpy(mask.reshape(-1)).to(dev)
+    fl = (m == 0)
+    fl3 = fl.repeat(3).view(3, -1)
+    dist = ndimage.distance_transform_edt(mask == 0).reshape(-1)
+    wall = torch.from_numpy(dist < 1.5).to(dev) & fl
+    inner = fl & ~wall
+    rms = float(u_ref.view(3, -1)[:, fl].pow(2).mean().sqrt())
+    g = torch.Generator(device=dev).manual_seed(rng_seed)
+    noise = torch.randn(3 * n ** 3, generator=g, device=dev, dtype=torch.float64)
+    smooth = _smooth(noise, fl3, n)
+    smooth = smooth / smooth.view(3, -1)[:, fl].pow(2).mean().sqrt()
+    u_pred = net.predict_velocity(m, n, WS.G_OVER_NU, phi)
+
+    def on(sel):
+        return sel.double().repeat(3)
+
+    def start_err(u0):
+        a = u0.view(3, -1)[:, fl]
+        b = u_ref.view(3, -1)[:, fl]
+        return float((a - b).norm() / b.norm())
+
+    starts = {
+        "cold (rest)": None,
+        "exact velocity, rho = 1": u_ref,
+        "exact velocity and density": (u_ref, rho_ref),
+        "0.8 x exact velocity": 0.8 * u_ref,
+        "exact + 10% voxel noise, interior": u_ref + 0.1 * rms * noise * on(inner),
+        "exact + 10% voxel noise, wall layer": u_ref + 0.1 * rms * noise * on(wall),
+        "exact + 10% noise smoothed over ~3 voxels": u_ref + 0.1 * rms * smooth * on(fl),
+        "network prediction": u_pred,
+        "prediction, wall layer exact": torch.where(on(wall) > 0, u_ref, u_pred),
+    }
+    rows = {}
+    for name, s0 in starts.items():
+        if s0 is None:
+            r = _run(mask, u_ref_mean)
+            r["start_rel_l2"] = 1.0
+        elif isinstance(s0, tuple):
+            r = _run(mask, u_ref_mean, s0[0].contiguous(), s0[1].contiguous())
+            r["start_rel_l2"] = start_err(s0[0])
+        else:
+            r = _run(mask, u_ref_mean, s0.contiguous())
+            r["start_rel_l2"] = start_err(s0)
+        rows[name] = r
+    # cold start rescaled to a final mean flux after T0 updates: the flow
+    # part f - w of every population is scaled (the Stokes state is linear
+    # in the drive, its non-equilibrium part and density deviation included)
+    w = _lattice(np.zeros((2, 2, 2), np.uint8)).export()[0]   # rest state = weights
+    pred_flux = float(u_pred.view(3, -1)[0].sum())
+    flm = mask.reshape(-1) == 0
+    for label, target in (("predicted", pred_flux), ("exact", true_flux)):
+        for t0 in (400,):
+            lat = _lattice(mask)
+            lat.step(t0)
+            a = target / lat.macroscopic()["momentum"][0]
+            f = lat.export()
+            f[flm] = w + a * (f[flm] - w)
+            lat.import_(f)
+            r = _run(mask, u_ref_mean, lat=lat)
+            r["steps"] += t0
+            r["scale"] = a
+            rows["cold, flow rescaled to the %s mean flux after %d updates" % (label, t0)] = r
+    return {"n": n, "seed": seed, "porosity": phi,
+            "prediction_flux_rel_err": pred_flux / true_flux - 1.0, "rows": rows}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sizes", default="64,128")
+    ap.add_argument("--seeds", default="100000,100001")
+    ap.add_argument("--weights", default=None, help="network weights (default: the packaged ones)")
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    import os
+    from .surrogate import UNet
+    path = args.weights or os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                                        "unet_porous64.npz")
+    net = UNet.load(path)
+    out = []
+    for n in [int(v) for v in args.sizes.split(",")]:
+        for seed in [int(v) for v in args.seeds.split(",")]:
+            res = study_box(net, n, seed)
+            out.append(res)
+            print("%d^3 seed %d porosity %.3f:" % (n, seed, res["porosity"]), flush=True)
+            for name, r in res["rows"].items():
+                print("   %-58s start err %.3f  %6d updates (%s)  end err %.1e"
+                      % (name, r.get("start_rel_l2", float("nan")), r["steps"], r["reason"],
+                         r["end_rel_l2"]), flush=True)
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump(out, fh, indent=1)
+    return out
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
