@@ -15,7 +15,8 @@
  * reduced), Sect. 3 "Lattice Representation", in
  * structure-of-arrays or array-of-structures layout (Sect. 3 "Data Layout").
  * Bounce-back is full-way or half-way (Sect. 2, Sect. 3.2); periodicity is
- * part of the index arithmetic or of the adjacency list (Sect. 3.2).
+ * part of the index arithmetic or of the adjacency list (Sect. 3.2), per
+ * axis (lbm_params.periodic).
  *
  * Conventions shared by every entry point:
  *  - Return value: LBM_OK (0) or a negative LBM_E* code.  No C++ exception
@@ -114,6 +115,17 @@ extern "C" {
 /* ---- parameter and buffer records ------------------------------------ */
 typedef struct {
   int32_t nx, ny, nz;       /* nodes per axis, walls included; each >= 1   */
+  uint32_t periodic;        /* bit 0 x, bit 1 y, bit 2 z: the axis wraps
+                               (Sect. 3.2).  On an axis whose bit is clear
+                               the box faces are walls: nodes beyond them
+                               count as solid.  Half-way bounce-back then
+                               reflects at the face, half a link outside
+                               the boundary layer.  Full-way bounce-back
+                               needs the two boundary layers of such an
+                               axis to be solid (else EINVAL); they keep
+                               the populations in transit, so the result
+                               is the same as with the axis wrapped.
+                               Other bits: EINVAL.                         */
   int32_t layout;           /* LBM_SOA | LBM_AOS (LIST_RIA requires SOA)   */
   int32_t addressing;       /* LBM_DIRECT | LBM_LIST | LBM_LIST_RIA        */
   int32_t storage;          /* LBM_F64 | LBM_F32_SHIFTED | LBM_F16_SHIFTED

@@ -11,7 +11,10 @@ Model readings (paper Sect. 2 and 3.2 name TRT, bounce-back and a constant
 body force; the formulas are the textbook ones): TRT relaxation of the
 symmetric/antisymmetric halves, second-order equilibrium, split forcing
 with u = (sum c f + g/2)/rho, full-way or half-way bounce-back, periodic
-wrap on every axis.
+wrap on the axes flagged periodic (all by default).  Beyond the faces of
+the other axes every node is solid: under half-way bounce-back a population
+leaving the box there is reflected at its node; full-way bounce-back needs
+solid nodes on those faces and wraps them (only solids exchange there).
 """
 from __future__ import annotations
 
@@ -37,8 +40,10 @@ def dot(a, b):
 
 
 class Brute:
-    def __init__(self, nx, ny, nz, is_solid, tau_plus, magic, g, fullway):
+    def __init__(self, nx, ny, nz, is_solid, tau_plus, magic, g, fullway,
+                 periodic=(True, True, True)):
         self.n = (nx, ny, nz)
+        self.periodic = tuple(bool(a) for a in periodic)
         self.is_solid = is_solid          # callable (x, y, z) -> bool
         self.lp = 1.0 / tau_plus
         self.lm = 1.0 / (0.5 + magic / (tau_plus - 0.5))
@@ -55,6 +60,10 @@ class Brute:
 
     def shift(self, p, c):
         return tuple((p[a] + c[a]) % self.n[a] for a in range(3))
+
+    def beyond_wall(self, p, c):
+        return any(not self.periodic[a] and not 0 <= p[a] + c[a] < self.n[a]
+                   for a in range(3))
 
     def moments(self, fn):
         rho = sum(fn[c] for c in self.vel)
@@ -97,7 +106,7 @@ class Brute:
         for p, fp in post.items():
             for c in self.vel:
                 q = self.shift(p, c)
-                if self.fullway or not self.is_solid(*q):
+                if self.fullway or not (self.beyond_wall(p, c) or self.is_solid(*q)):
                     new[q][c] = fp[c]
                 else:
                     new[p][neg(c)] = fp[c]

@@ -27,8 +27,15 @@
  *     arriving populations and send them back reversed one step later) or
  *     half-way (a population streaming into a solid node is reflected into
  *     the opposite direction of the node it left, in the same step).
- *   - The lattice is a 3-torus: every axis wraps; walls are solid nodes of
- *     the mask (Sect. 2 geometries include their wall layers).
+ *   - Periodicity (Sect. 3.2) per axis: ora_run wraps every axis (a
+ *     3-torus; walls are solid nodes of the mask, as the Sect. 2 geometries
+ *     include their wall layers).  ora_run_box takes a bit mask of the axes
+ *     that wrap; beyond the faces of the other axes every node counts as
+ *     solid.  Under half-way bounce-back a population that would leave the
+ *     box there is reflected like one aimed at a solid node.  Full-way
+ *     bounce-back keeps reflected populations inside solid nodes, so it
+ *     requires solid boundary layers on those axes and then wraps them
+ *     (only solid nodes exchange populations across such a face).
  *
  * Threads: the two passes carry OpenMP "parallel for" pragmas over nodes
  * (collide) and over z planes (stream).  A plain build ignores them; the
@@ -169,17 +176,41 @@ static int64_t ora_node(int64_t x, int64_t y, int64_t z, int nx, int ny,
   return ora_wrap(x, nx) + (int64_t)nx * (ora_wrap(y, ny) + (int64_t)ny * ora_wrap(z, nz));
 }
 
+/* 1 if coordinate v of an axis of n nodes lies outside the box and the
+   axis does not wrap (its bit in `periodic` is clear). */
+static int ora_outside(int64_t v, int n, unsigned periodic, int axis) {
+  return !((periodic >> axis) & 1u) && (v < 0 || v >= n);
+}
+
+/* 1 if every node of the two boundary layers of each non-wrapping axis is
+   solid. */
+static int ora_faces_solid(int nx, int ny, int nz, const uint8_t* mask,
+                           unsigned periodic) {
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        int on_face = (!(periodic & 1u) && (x == 0 || x == nx - 1)) ||
+                      (!(periodic & 2u) && (y == 0 || y == ny - 1)) ||
+                      (!(periodic & 4u) && (z == 0 || z == nz - 1));
+        if (on_face && mask[ora_node(x, y, z, nx, ny, nz)] == 0) return 0;
+      }
+  return 1;
+}
+
 /*
  * Advance the canonical state f[N][19] by nsteps (collide, then stream).
- * bounce: 0 = full-way, 1 = half-way.  Returns 0, or -1 on bad arguments
- * or allocation failure.
+ * bounce: 0 = full-way, 1 = half-way.  periodic: bit 0 x, 1 y, 2 z set for
+ * the axes that wrap.  Returns 0, or -1 on bad arguments (including
+ * full-way with a fluid node on a wall face) or allocation failure.
  */
-int ora_run(int nx, int ny, int nz, const uint8_t* mask, int bounce,
-            double tau_plus, double magic, const double* g, double* f,
-            int nsteps) {
+int ora_run_box(int nx, int ny, int nz, unsigned periodic, const uint8_t* mask,
+                int bounce, double tau_plus, double magic, const double* g,
+                double* f, int nsteps) {
   ora_tables();
   if (nx < 1 || ny < 1 || nz < 1 || !mask || !f || !g || nsteps < 0) return -1;
   if (!(tau_plus > 0.5) || !(magic > 0.0) || (bounce != 0 && bounce != 1)) return -1;
+  if (periodic > 7u) return -1;
+  if (bounce == 0 && !ora_faces_solid(nx, ny, nz, mask, periodic)) return -1;
   int64_t n_nodes = (int64_t)nx * ny * nz;
   double* post = (double*)malloc(sizeof(double) * ORA_Q * n_nodes);
   if (!post) return -1;
@@ -201,7 +232,8 @@ int ora_run(int nx, int ny, int nz, const uint8_t* mask, int bounce,
     /* stream */
     if (bounce == 1) memset(f, 0, sizeof(double) * ORA_Q * n_nodes);
     /* each target slot has one writer: f(x + c_i, i) from x, or, for a
-       solid target under half-way bounce-back, f(x, opp i) from x itself */
+       solid target (or one beyond a wall face) under half-way bounce-back,
+       f(x, opp i) from x itself */
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z)
       for (int y = 0; y < ny; ++y)
@@ -209,9 +241,12 @@ int ora_run(int nx, int ny, int nz, const uint8_t* mask, int bounce,
           int64_t n = ora_node(x, y, z, nx, ny, nz);
           if (bounce == 1 && mask[n] != 0) continue;
           for (int i = 0; i < ORA_Q; ++i) {
-            int64_t t = ora_node(x + ORA_C[i][0], y + ORA_C[i][1],
-                                 z + ORA_C[i][2], nx, ny, nz);
-            if (bounce == 0 || mask[t] == 0)
+            int64_t tx = x + ORA_C[i][0], ty = y + ORA_C[i][1], tz = z + ORA_C[i][2];
+            int beyond = ora_outside(tx, nx, periodic, 0) ||
+                         ora_outside(ty, ny, periodic, 1) ||
+                         ora_outside(tz, nz, periodic, 2);
+            int64_t t = ora_node(tx, ty, tz, nx, ny, nz);
+            if (bounce == 0 || (!beyond && mask[t] == 0))
               f[ORA_Q * t + i] = post[ORA_Q * n + i];
             else
               f[ORA_Q * n + ora_opposite(i)] = post[ORA_Q * n + i];
@@ -220,6 +255,13 @@ int ora_run(int nx, int ny, int nz, const uint8_t* mask, int bounce,
   }
   free(post);
   return 0;
+}
+
+/* ora_run_box with every axis wrapping. */
+int ora_run(int nx, int ny, int nz, const uint8_t* mask, int bounce,
+            double tau_plus, double magic, const double* g, double* f,
+            int nsteps) {
+  return ora_run_box(nx, ny, nz, 7u, mask, bounce, tau_plus, magic, g, f, nsteps);
 }
 
 /* Density and velocity fields of the canonical state; solids report 0. */

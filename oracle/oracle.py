@@ -72,6 +72,10 @@ def _load(omp: bool = False):
                                 ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                 dp, dp, ctypes.c_int]
         lib.ora_run.restype = ctypes.c_int
+        lib.ora_run_box.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                    u8p, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                    dp, dp, ctypes.c_int]
+        lib.ora_run_box.restype = ctypes.c_int
         lib.ora_macroscopic.argtypes = [ctypes.c_int64, u8p, dp, dp, dp, dp]
         lib.ora_rest_state.argtypes = [ctypes.c_int64, u8p, ctypes.c_int, dp]
         _libs[omp] = lib
@@ -121,17 +125,20 @@ def rest_state(mask: np.ndarray, bounce: int) -> np.ndarray:
 
 
 def run(mask: np.ndarray, f: np.ndarray, steps: int, tau_plus: float,
-        magic: float, g, bounce: int, omp: bool = False) -> np.ndarray:
+        magic: float, g, bounce: int, omp: bool = False, periodic: int = 7) -> np.ndarray:
     """Advance a copy of the canonical state ``f`` by ``steps`` updates.
 
     bounce: 0 = full-way, 1 = half-way.  ``omp``: run the OpenMP build
-    (threads from OMP_NUM_THREADS; same results bit for bit)."""
+    (threads from OMP_NUM_THREADS; same results bit for bit).  ``periodic``:
+    bit mask of the axes that wrap (bit 0 x, 1 y, 2 z); the faces of the
+    others are walls (Sect. 3.2 periodicity, read per axis)."""
     m = np.ascontiguousarray(mask, dtype=np.uint8)
     nz, ny, nx = m.shape
     out = np.array(f, dtype=np.float64, order="C", copy=True).reshape(m.size, Q)
     gg = np.ascontiguousarray(g, dtype=np.float64)
-    rc = _load(omp).ora_run(nx, ny, nz, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
-                         bounce, tau_plus, magic, _dp(gg), _dp(out), steps)
+    rc = _load(omp).ora_run_box(nx, ny, nz, periodic,
+                                m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                bounce, tau_plus, magic, _dp(gg), _dp(out), steps)
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return out
@@ -157,7 +164,7 @@ def residual(u_new: np.ndarray, u_old: np.ndarray, fluid: np.ndarray) -> float:
 
 
 def run_to_steady(mask, f, tau_plus, magic, g, bounce, tol, check_every=100,
-                  max_steps=10_000_000, omp=False):
+                  max_steps=10_000_000, omp=False, periodic=7):
     """Iterate in chunks of ``check_every`` until the velocity residual
     between chunks falls below ``tol``.  Returns (f, steps, residual)."""
     fluid = np.asarray(mask).reshape(-1) == 0
@@ -165,7 +172,7 @@ def run_to_steady(mask, f, tau_plus, magic, g, bounce, tol, check_every=100,
     steps = 0
     r = float("inf")
     while steps < max_steps:
-        f = run(mask, f, check_every, tau_plus, magic, g, bounce, omp=omp)
+        f = run(mask, f, check_every, tau_plus, magic, g, bounce, omp=omp, periodic=periodic)
         steps += check_every
         _, u = macroscopic(mask, f, g)
         r = residual(u, u_old, fluid)

@@ -20,7 +20,7 @@ static unsigned reduce_grid(int64_t n) {
 }
 
 
-template <class ST, int LAYOUT, int ADDR, int BB>
+template <class ST, int LAYOUT, int ADDR, int BB, int WALLS>
 __global__ void __launch_bounds__(kReduceBlock)
 k_moments(const typename ST::T* __restrict__ src, View v, int64_t n_sites, int64_t n_nodes,
           double gx, double gy, double gz, double* __restrict__ rho_out,
@@ -33,7 +33,7 @@ k_moments(const typename ST::T* __restrict__ src, View v, int64_t n_sites, int64
        s += (int64_t)gridDim.x * blockDim.x) {
     const int64_t node = ADDR == LBM_LIST ? (int64_t)v.fluid_index[s] : s;
     double f[Q];
-    if (!gather_canonical<ST, LAYOUT, ADDR, BB>(src, v, node, f)) continue;
+    if (!gather_canonical<ST, LAYOUT, ADDR, BB, WALLS>(src, v, node, f)) continue;
     double rho, ux, uy, uz, jx, jy, jz;
     moments_f64(f, gx, gy, gz, rho, ux, uy, uz, jx, jy, jz);
     acc[M_MASS] += rho;
@@ -73,14 +73,16 @@ hipError_t launch_moments(lbm_ctx* c, const void* src, double* rho_out, double* 
                           int residual_mode, double* partials, int64_t* n_blocks_out) {
   const unsigned grid = reduce_grid(c->s.n_sites);
   *n_blocks_out = grid;
-  return dispatch(c->p, [&](auto st, auto lay, auto addr, auto bb) -> hipError_t {
-    using ST = decltype(st);
-    hipLaunchKernelGGL((k_moments<ST, decltype(lay)::value, decltype(addr)::value,
-                                  decltype(bb)::value>),
-                       dim3(grid), dim3(kReduceBlock), 0, c->stream, (const typename ST::T*)src,
-                       view_of(c), c->s.n_sites, c->s.n_nodes, c->p.g[0], c->p.g[1], c->p.g[2],
-                       rho_out, u_out, c->b.u_prev, residual_mode, partials);
-    return hipGetLastError();
+  return with_walls(c->p, [&](auto walls) -> hipError_t {
+    return dispatch(c->p, [&](auto st, auto lay, auto addr, auto bb) -> hipError_t {
+      using ST = decltype(st);
+      hipLaunchKernelGGL((k_moments<ST, decltype(lay)::value, decltype(addr)::value,
+                                    decltype(bb)::value, decltype(walls)::value>),
+                         dim3(grid), dim3(kReduceBlock), 0, c->stream, (const typename ST::T*)src,
+                         view_of(c), c->s.n_sites, c->s.n_nodes, c->p.g[0], c->p.g[1], c->p.g[2],
+                         rho_out, u_out, c->b.u_prev, residual_mode, partials);
+      return hipGetLastError();
+    });
   });
 }
 
@@ -116,7 +118,7 @@ __device__ double duct_ux(int y, int z, int ny, int nz, double gx, double nu) {
   return 16.0 * a * a * gx / (nu * M_PI * M_PI * M_PI) * sum;
 }
 
-template <class ST, int LAYOUT, int ADDR, int BB>
+template <class ST, int LAYOUT, int ADDR, int BB, int WALLS>
 __global__ void __launch_bounds__(kReduceBlock)
 k_verify(const typename ST::T* __restrict__ src, View v, int64_t n_sites, double gx, double gy,
          double gz, VerifyArgs a, double* __restrict__ partials) {
@@ -128,7 +130,7 @@ k_verify(const typename ST::T* __restrict__ src, View v, int64_t n_sites, double
     const int64_t node = ADDR == LBM_LIST ? (int64_t)v.fluid_index[s] : s;
     if (ADDR == LBM_DIRECT && v.mask[node] != 0) continue;
     double f[Q];
-    if (!gather_canonical<ST, LAYOUT, ADDR, BB>(src, v, node, f)) continue;
+    if (!gather_canonical<ST, LAYOUT, ADDR, BB, WALLS>(src, v, node, f)) continue;
     double rho, ux, uy, uz, jx, jy, jz;
     moments_f64(f, gx, gy, gz, rho, ux, uy, uz, jx, jy, jz);
     int x, y, z;
@@ -167,13 +169,15 @@ hipError_t launch_verify(lbm_ctx* c, const void* src, int kind, const double* re
   a.nu = (c->p.tau_plus - 0.5) / 3.0;
   a.ref = ref_dev;
   a.n_nodes = c->s.n_nodes;
-  return dispatch(c->p, [&](auto st, auto lay, auto addr, auto bb) -> hipError_t {
-    using ST = decltype(st);
-    hipLaunchKernelGGL((k_verify<ST, decltype(lay)::value, decltype(addr)::value,
-                                 decltype(bb)::value>),
-                       dim3(grid), dim3(kReduceBlock), 0, c->stream, (const typename ST::T*)src,
-                       view_of(c), c->s.n_sites, c->p.g[0], c->p.g[1], c->p.g[2], a, partials);
-    return hipGetLastError();
+  return with_walls(c->p, [&](auto walls) -> hipError_t {
+    return dispatch(c->p, [&](auto st, auto lay, auto addr, auto bb) -> hipError_t {
+      using ST = decltype(st);
+      hipLaunchKernelGGL((k_verify<ST, decltype(lay)::value, decltype(addr)::value,
+                                   decltype(bb)::value, decltype(walls)::value>),
+                         dim3(grid), dim3(kReduceBlock), 0, c->stream, (const typename ST::T*)src,
+                         view_of(c), c->s.n_sites, c->p.g[0], c->p.g[1], c->p.g[2], a, partials);
+      return hipGetLastError();
+    });
   });
 }
 

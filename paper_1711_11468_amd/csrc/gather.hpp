@@ -4,8 +4,9 @@
 // A pull buffer holds post-collision populations.  The canonical state of a
 // node is what one streaming pass delivers to it: population i comes from
 // the neighbour x - c_i (periodic wrap), or, under half-way bounce-back when
-// that neighbour is solid, from the node's own opposite slot.  For the list
-// representation the adjacency list already encodes exactly this.
+// that neighbour is solid or lies beyond a wall face (an axis that does not
+// wrap), from the node's own opposite slot.  For the list representation the
+// adjacency list already encodes exactly this.
 #pragma once
 
 #include "d3q19.hpp"
@@ -25,6 +26,7 @@ struct View {
                            // even number of updates (canonical in place);
                            // 2: AA lattice after an odd number (post-collision,
                            // stored reversed at the node)
+  uint32_t periodic;       // bit a set: axis a wraps; else its faces are walls
 };
 
 template <int LAYOUT>
@@ -37,6 +39,24 @@ __device__ __forceinline__ int64_t wrap_node(const View& v, int x, int y, int z)
   y = y < 0 ? y + v.ny : (y >= v.ny ? y - v.ny : y);
   z = z < 0 ? z + v.nz : (z >= v.nz ? z - v.nz : z);
   return (int64_t)x + (int64_t)v.nx * ((int64_t)y + (int64_t)v.ny * z);
+}
+
+// True when (x, y, z), each coordinate at most one step outside the box,
+// lies beyond a face of an axis that does not wrap (such nodes are solid).
+// WALLS = 0 compiles the fully periodic lattice, where no node does.
+// Callers combine it with the solid flag of the wrapped node by a
+// branch-free select after an unconditional (in-bounds) load: gfx950 code
+// for a short-circuit form that loads the flag only inside the branch
+// reused the register of the other branch's load address for the flag and
+// then loaded through it on lanes with a solid neighbour.
+template <int WALLS>
+__device__ __forceinline__ bool beyond_wall(const View& v, int x, int y, int z) {
+  if (!WALLS) return false;
+  const uint32_t p = v.periodic;
+  const bool bx = ((p & 1u) == 0) & ((x < 0) | (x >= v.nx));
+  const bool by = ((p & 2u) == 0) & ((y < 0) | (y >= v.ny));
+  const bool bz = ((p & 4u) == 0) & ((z < 0) | (z >= v.nz));
+  return bx | by | bz;
 }
 
 __device__ __forceinline__ void node_xyz(const View& v, int64_t n, int& x, int& y, int& z) {
@@ -52,12 +72,14 @@ __device__ __forceinline__ void node_xyz(const View& v, int64_t n, int& x, int& 
 // neighbour x - c_i, else slot opp(i) of the node) unless the lattice is an
 // AA lattice after an odd number of updates (slot opp(i) of the neighbour,
 // else slot i of the node).
-template <int LAYOUT>
+template <int LAYOUT, int WALLS>
 __device__ __forceinline__ int64_t list_slot(const View& v, int m, int i) {
   if (v.adj) return v.adj[(int64_t)(i - 1) * v.adj_stride + m];
   int x, y, z;
   node_xyz(v, v.fluid_index[m], x, y, z);
-  const int t = v.node_map[wrap_node(v, x - Vel::cx[i], y - Vel::cy[i], z - Vel::cz[i])];
+  const int sx = x - Vel::cx[i], sy = y - Vel::cy[i], sz = z - Vel::cz[i];
+  const int tw = v.node_map[wrap_node(v, sx, sy, sz)];
+  const int t = beyond_wall<WALLS>(v, sx, sy, sz) ? -1 : tw;
   const bool aa = v.aa == 2;
   return t >= 0 ? vslot<LAYOUT>(t, aa ? Vel::opp[i] : i, v.stride)
                 : vslot<LAYOUT>(m, aa ? i : Vel::opp[i], v.stride);
@@ -85,7 +107,7 @@ __device__ __forceinline__ typename ST::T rest_value(int i) {
 
 // Canonical populations of full node index `node`; false if it holds none
 // (solid under half-way bounce-back).
-template <class ST, int LAYOUT, int ADDR, int BB>
+template <class ST, int LAYOUT, int ADDR, int BB, int WALLS>
 __device__ __forceinline__ bool gather_canonical(const typename ST::T* __restrict__ src,
                                                  const View& v, int64_t node, double (&f)[Q]) {
   if (ADDR == LBM_LIST) {
@@ -94,7 +116,7 @@ __device__ __forceinline__ bool gather_canonical(const typename ST::T* __restric
     f[0] = to_f64<ST>(src[vslot<LAYOUT>(m, 0, v.stride)], 0, v);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const int64_t at = v.aa == 1 ? vslot<LAYOUT>(m, i, v.stride) : list_slot<LAYOUT>(v, m, i);
+      const int64_t at = v.aa == 1 ? vslot<LAYOUT>(m, i, v.stride) : list_slot<LAYOUT, WALLS>(v, m, i);
       f[i] = to_f64<ST>(src[at], i, v);
     }
     return true;
@@ -110,12 +132,15 @@ __device__ __forceinline__ bool gather_canonical(const typename ST::T* __restric
   node_xyz(v, node, x, y, z);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const int64_t sn = wrap_node(v, x - Vel::cx[i], y - Vel::cy[i], z - Vel::cz[i]);
+    const int sx = x - Vel::cx[i], sy = y - Vel::cy[i], sz = z - Vel::cz[i];
+    const int64_t sn = wrap_node(v, sx, sy, sz);
     // two-lattice pull buffer: slot i of the neighbour; AA after an odd
     // number of updates: slot opp(i) of the neighbour (stored reversed)
     int64_t at = vslot<LAYOUT>(sn, v.aa == 2 ? Vel::opp[i] : i, v.stride);
-    if (BB == LBM_HALFWAY && i != 0 && v.mask[sn] != 0)
-      at = vslot<LAYOUT>(node, v.aa == 2 ? i : Vel::opp[i], v.stride);
+    if (BB == LBM_HALFWAY && i != 0) {
+      const bool solid = (v.mask[sn] != 0) | beyond_wall<WALLS>(v, sx, sy, sz);
+      if (solid) at = vslot<LAYOUT>(node, v.aa == 2 ? i : Vel::opp[i], v.stride);
+    }
     f[i] = to_f64<ST>(src[at], i, v);
   }
   return true;
@@ -167,6 +192,15 @@ namespace lbm {
 
 template <int V>
 using IC = std::integral_constant<int, V>;
+
+// Call f(walls) with walls = IC<0> for a fully periodic lattice and IC<1>
+// when some axis has wall faces; the I/O and diagnostics kernels take it as
+// their WALLS parameter.
+template <class F>
+hipError_t with_walls(const lbm_params& p, F&& f) {
+  if (p.periodic == 7u) return f(IC<0>{});
+  return f(IC<1>{});
+}
 
 // Call f(storage_tag, layout, addressing, bounce) with compile-time tags for
 // the parameter combination of p (both lists imply half-way and share the

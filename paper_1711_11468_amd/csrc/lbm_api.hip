@@ -48,6 +48,7 @@ static int validate(const lbm_params* p) {
   if (!p) { set_error("params is NULL"); return LBM_EINVAL; }
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) { set_error("dimensions must be >= 1"); return LBM_EINVAL; }
   if ((int64_t)p->ny * p->nz > 0x7fffffffLL) { set_error("ny*nz too large"); return LBM_EOVERFLOW; }
+  if (p->periodic & ~7u) { set_error("periodic takes bits 0 (x), 1 (y) and 2 (z) only"); return LBM_EINVAL; }
   if (!(p->tau_plus > 0.5)) { set_error("tau_plus must exceed 1/2"); return LBM_EINVAL; }
   if (!(p->magic_lambda > 0.0)) { set_error("magic_lambda must be positive"); return LBM_EINVAL; }
   if (p->layout != LBM_SOA && p->layout != LBM_AOS) { set_error("bad layout"); return LBM_EINVAL; }
@@ -91,6 +92,34 @@ static int validate(const lbm_params* p) {
   return LBM_OK;
 }
 
+// Full-way bounce-back stores the populations that enter a solid node, so a
+// wall face needs solid nodes to hold them: on every axis that does not wrap,
+// both boundary layers must be solid.  The sweeps still wrap such an axis;
+// only solid boundary nodes then exchange populations across it, and those
+// never reach a fluid node, so the fluid sees walls at the faces.
+static int check_faces(const lbm_params* p, const uint8_t* mask) {
+  if (p->bounce != LBM_FULLWAY || p->periodic == 7u) return LBM_OK;
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const char* name = "xyz";
+  for (int a = 0; a < 3; ++a) {
+    if (p->periodic & (1u << a)) continue;
+    const int n = a == 0 ? nx : (a == 1 ? ny : nz);
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const int c = a == 0 ? x : (a == 1 ? y : z);
+          if (c != 0 && c != n - 1) continue;
+          if (mask[x + (int64_t)nx * (y + (int64_t)ny * z)] == 0) {
+            set_error("full-way bounce-back with %c not periodic needs solid boundary layers %c = 0 "
+                      "and %c = %d; node (%d, %d, %d) is fluid",
+                      name[a], name[a], name[a], n - 1, x, y, z);
+            return LBM_EINVAL;
+          }
+        }
+  }
+  return LBM_OK;
+}
+
 // Byte offsets of the run tables inside the ria buffer (layout in lbm_ctx).
 struct RiaLayout {
   int64_t run_stride, start_off, adj_off, chunk_off, delta_off, bytes;
@@ -119,16 +148,21 @@ static int64_t find_runs(const lbm_params* p, const uint8_t* mask, uint8_t* is_s
   for (int z = 0; z < nz; ++z) {
     for (int y = 0; y < ny; ++y) {
       const int64_t row = (int64_t)nx * (y + (int64_t)ny * z);
-      // the nine source rows (y - c_y, z - c_z) of this row
+      // the nine source rows (y - c_y, z - c_z) of this row; NULL for a row
+      // beyond a wall face (all of it counts as solid)
       const uint8_t* src_row[Q];
       for (int i = 0; i < Q; ++i) {
-        const int sy = (y - Vel::cy[i] + ny) % ny, sz = (z - Vel::cz[i] + nz) % nz;
-        src_row[i] = mask + (int64_t)nx * (sy + (int64_t)ny * sz);
+        const int ty = y - Vel::cy[i], tz = z - Vel::cz[i];
+        const bool out = (!(p->periodic & 2u) && (ty < 0 || ty >= ny)) ||
+                         (!(p->periodic & 4u) && (tz < 0 || tz >= nz));
+        const int sy = (ty + ny) % ny, sz = (tz + nz) % nz;
+        src_row[i] = out ? nullptr : mask + (int64_t)nx * (sy + (int64_t)ny * sz);
       }
       for (int x = 0; x < nx; ++x) {
         if (mask[row + x] != 0) continue;
         bool start = x < 2 || x > nx - 2 || mask[row + x - 1] != 0;
         for (int i = 1; i < Q && !start; ++i) {
+          if (!src_row[i]) continue;
           const int sx = x - Vel::cx[i];
           start = (src_row[i][sx] != 0) != (src_row[i][sx - 1] != 0);
         }
@@ -247,6 +281,8 @@ int lbm_plan(const lbm_params* params, const uint8_t* mask_host, lbm_sizes* out)
   if (!mask_host || !out) { set_error("mask_host and out must be non-NULL"); return LBM_EINVAL; }
   const int64_t N = (int64_t)params->nx * params->ny * params->nz;
   if (N >= 0x7fffffffLL) { set_error("lattice too large"); return LBM_EOVERFLOW; }
+  rc = check_faces(params, mask_host);
+  if (rc) return rc;
   const int64_t runs = params->addressing == LBM_LIST_RIA ? find_runs(params, mask_host, nullptr) : 0;
   return plan_sizes(params, count_fluid(params, mask_host), runs, out);
 }
@@ -261,6 +297,8 @@ int lbm_init_geometry(lbm_ctx** out, const lbm_params* params, const uint8_t* ma
   lbm_sizes s;
   const int64_t N = (int64_t)params->nx * params->ny * params->nz;
   if (N >= 0x7fffffffLL) { set_error("lattice too large"); return LBM_EOVERFLOW; }
+  rc = check_faces(params, mask_host);
+  if (rc) return rc;
   const bool ria = params->addressing == LBM_LIST_RIA;
   std::vector<uint8_t> run_starts;
   int64_t runs = 0;

@@ -35,7 +35,7 @@ ELEM_BYTES = {F64: 8, F32_SHIFTED: 4, F16_SHIFTED: 2, F16_SHIFTED_SR: 2}
 
 class Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("layout", ctypes.c_int32), ("addressing", ctypes.c_int32),
+                ("periodic", ctypes.c_uint32), ("layout", ctypes.c_int32), ("addressing", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("bounce", ctypes.c_int32),
                 ("f16_scale_log2", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("cu_slots", ctypes.c_int32),
@@ -146,10 +146,17 @@ def _check(code, where):
 
 def make_params(shape, tau_plus=0.8, magic=3.0 / 16.0, g=(0.0, 0.0, 0.0), layout="soa",
                 addressing="direct", storage="f64", bounce="fullway", f16_scale_log2=14,
-                block=0, pad=-1, cu_slots=0, propagation="os") -> Params:
+                block=0, pad=-1, cu_slots=0, propagation="os", periodic="xyz") -> Params:
+    """``periodic`` names the axes that wrap ("xyz", "x", "" ...) or gives
+    the bit mask (bit 0 x, 1 y, 2 z); the faces of the other axes are walls."""
     nz, ny, nx = shape
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
+    if isinstance(periodic, str):
+        if set(periodic) - set("xyz"):
+            raise ValueError(f"periodic axes must be drawn from 'xyz', got {periodic!r}")
+        periodic = sum(1 << "xyz".index(a) for a in set(periodic))
+    p.periodic = int(periodic)
     p.layout = _LAYOUTS[layout]
     p.addressing = _ADDR[addressing]
     p.storage = _STORAGE[storage]

@@ -141,7 +141,20 @@ def test_plan_degenerate_geometries():
     assert push.bytes_per_update == pull.bytes_per_update and push.pdf_bytes == pull.pdf_bytes
 
 
-def _runs_by_definition(mask):
+def _source_solid(mask, ci, periodic):
+    """Per node: is the pull source x - c_i solid?  Beyond a face of an axis
+    whose periodic bit is clear every node counts as solid."""
+    nz, ny, nx = mask.shape
+    z, y, x = np.indices(mask.shape)
+    sx, sy, sz = x - ci[0], y - ci[1], z - ci[2]
+    out = np.zeros(mask.shape, dtype=bool)
+    for a, (v, n) in enumerate(((sx, nx), (sy, ny), (sz, nz))):
+        if not periodic >> a & 1:
+            out |= (v < 0) | (v >= n)
+    return out | (mask[sz % nz, sy % ny, sx % nx] != 0)
+
+
+def _runs_by_definition(mask, periodic=7):
     """Run starts of the run-length list, from its definition, in numpy:
     a fluid node continues the run of its x-predecessor when that node is
     fluid, neither pull source of the pair wraps in x (2 <= x <= nx-2), and
@@ -155,12 +168,12 @@ def _runs_by_definition(mask):
     start[:, :, nx - 1:] = True
     start |= np.roll(solid, 1, axis=2)
     for i in range(1, 19):
-        src = np.roll(solid, (c[i][2], c[i][1], c[i][0]), axis=(0, 1, 2))  # status of x - c_i
+        src = _source_solid(mask, c[i], periodic)
         start |= src != np.roll(src, 1, axis=2)
     return start[~solid]
 
 
-def _pull_adjacency(mask):
+def _pull_adjacency(mask, periodic=7):
     """Pull slots (direction-major, list order) of every fluid node."""
     from oracle import oracle as O
     c = O.table()[0]
@@ -175,9 +188,66 @@ def _pull_adjacency(mask):
     adj = np.empty((19, nf), dtype=np.int64)
     for i in range(19):
         sn = ((x - c[i][0]) % nx) + nx * (((y - c[i][1]) % ny) + ny * ((z - c[i][2]) % nz))
-        t = nmap[sn]
+        t = np.where(_source_solid(mask, c[i], periodic).reshape(-1)[fl], -1, nmap[sn])
         adj[i] = np.where(t >= 0, i * nf + t, opp[i] * nf + m)
     return adj
+
+
+@pytest.mark.parametrize("periodic", [0b000, 0b001, 0b110, 0b011])
+def test_ria_runs_wall_faces(periodic):
+    """With axes that do not wrap, sources beyond their faces count as
+    solid: the run count still equals the definition's, and every run still
+    advances each pull slot by one."""
+    mask = I.random_solid_mask(40, 9, 7, seed=2, fraction=0.25)
+    start = _runs_by_definition(mask, periodic)
+    s = lbm.plan(mask, addressing="ria", bounce="halfway", periodic=periodic)
+    assert s.n_runs == int(start.sum())
+    adj = _pull_adjacency(mask, periodic)
+    cont = ~start
+    cont[0] = False
+    idx = np.flatnonzero(cont)
+    assert np.array_equal(adj[:, idx], adj[:, idx - 1] + 1)
+    # x-boundary nodes start runs in any case; walls on y or z faces change them
+    if periodic & 0b110 != 0b110:
+        assert s.n_runs != lbm.plan(mask, addressing="ria", bounce="halfway").n_runs
+
+
+def test_periodic_bits_validated():
+    """periodic takes bits 0..2; full-way bounce-back needs solid boundary
+    layers on every axis that does not wrap; half-way needs none."""
+    slab = I.slab_mask(6, 5, 7)  # plates: the z boundary layers
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.plan(slab, periodic=8)
+    assert e.value.code == lbm.EINVAL
+    lbm.plan(slab, bounce="fullway", periodic="xy")
+    for per in ("xz", "yz", ""):
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.plan(slab, bounce="fullway", periodic=per)
+        assert e.value.code == lbm.EINVAL
+        lbm.plan(slab, bounce="halfway", periodic=per)
+    with pytest.raises(ValueError):
+        lbm.make_params(slab.shape, periodic="xw")
+
+
+def test_params_struct_matches_header(tmp_path):
+    """The binding's lbm_params mirror has the header's size and offsets
+    (compiled with the host C compiler against include/lbm.h)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f[0] for f in lbm.Params._fields_]
+    src = tmp_path / "layout.c"
+    body = "".join('printf("%s %%zu\\n", offsetof(lbm_params, %s));' % (f, f) for f in fields)
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbm.h"\n'
+                   'int main(void) { printf("size %%zu\\n", sizeof(lbm_params)); %s return 0; }\n' % body)
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    assert int(got["size"]) == ctypes.sizeof(lbm.Params)
+    for f in fields:
+        assert int(got[f]) == getattr(lbm.Params, f).offset, f
 
 
 @pytest.mark.parametrize("which", ["duct", "random", "spheres", "tiny"])

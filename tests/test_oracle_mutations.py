@@ -27,8 +27,11 @@ MUTATIONS = {
                            "double lm = lp;"),
     "tau_minus_formula": ("return 0.5 + magic / (tau_plus - 0.5);",
                           "return 0.5 + magic * (tau_plus - 0.5);"),
-    "stream_direction": ("int64_t t = ora_node(x + ORA_C[i][0], y + ORA_C[i][1],",
-                         "int64_t t = ora_node(x - ORA_C[i][0], y + ORA_C[i][1],"),
+    "stream_direction": ("int64_t tx = x + ORA_C[i][0],", "int64_t tx = x - ORA_C[i][0],"),
+    "wall_face_ignored_on_x": ("int beyond = ora_outside(tx, nx, periodic, 0) ||",
+                               "int beyond = 0 * ora_outside(tx, nx, periodic, 0) ||"),
+    "wall_face_wrong_axis_bit": ("return !((periodic >> axis) & 1u)", "return !((periodic >> 0) & 1u)"),
+    "wall_face_off_by_one": ("(v < 0 || v >= n)", "(v < 0 || v > n)"),
     "halfway_reflect_index": ("f[ORA_Q * n + ora_opposite(i)] = post[ORA_Q * n + i];",
                               "f[ORA_Q * n + i] = post[ORA_Q * n + i];"),
     "fullway_no_reversal": ("pn[i] = fn[ora_opposite(i)];", "pn[i] = fn[i];"),
@@ -48,6 +51,9 @@ FAST_PINS = [
     (P.test_slab_closed_form, {"magic": 1 / 4, "bounce": 1}),
     (P.test_brute_force_4cubed, {"bounce": 0}),
     (P.test_brute_force_4cubed, {"bounce": 1}),
+    (P.test_brute_force_wall_faces, {"periodic": 0b001}),
+    (P.test_brute_force_wall_faces, {"periodic": 0b110}),
+    (P.test_wall_faces_equal_solid_layers, {"periodic": 0b101}),
 ]
 
 
@@ -64,7 +70,7 @@ def test_planted_mistake_is_caught(name, tmp_path, monkeypatch):
     real = O._load()  # the real library, whose argtypes are set
     lib = ctypes.CDLL(str(so))
     for fn in ("ora_table", "ora_equilibrium", "ora_moments", "ora_collide_node",
-               "ora_tau_minus", "ora_run", "ora_macroscopic", "ora_rest_state"):
+               "ora_tau_minus", "ora_run", "ora_run_box", "ora_macroscopic", "ora_rest_state"):
         getattr(lib, fn).argtypes = getattr(real, fn).argtypes
         getattr(lib, fn).restype = getattr(real, fn).restype
     monkeypatch.setitem(O._libs, False, lib)
@@ -74,4 +80,7 @@ def test_planted_mistake_is_caught(name, tmp_path, monkeypatch):
             fn(**kw)
         except (AssertionError, ValueError, FloatingPointError, KeyError, IndexError):
             failed.append(fn.__name__)
+            # one catch suffices; a mutant with a broken table can also
+            # index out of bounds, so it is run no further than needed
+            break
     assert failed, "no pin caught the planted mistake %s" % name

@@ -321,3 +321,96 @@ def test_oracle_corner_limit_cycle(bounce, period):
     r_period = nrm(us[period] - us[0]) / nrm(us[0])
     assert r_step > 1e-4
     assert r_period < 1e-10
+
+
+# ---- wall faces: axes that do not wrap (periodicity per axis, Sect. 3.2) ----
+
+BITS = {0b000: "none", 0b001: "x", 0b110: "yz", 0b101: "xz", 0b010: "y"}
+
+
+@pytest.mark.parametrize("periodic", sorted(BITS))
+def test_brute_force_wall_faces(periodic):
+    """Half-way bounce-back at the faces of the axes that do not wrap: the C
+    oracle agrees with the table-free brute force on a 4x5x3 box (unequal
+    sides, so an axis mix-up shows) with 15 % random solids and a force."""
+    c, w, _ = O.table()
+    nx, ny, nz = 4, 5, 3
+    mask = I.random_solid_mask(nx, ny, nz, seed=5, fraction=0.15)
+    n = mask.size
+    f0 = w[None, :] * (1 + 0.01 * I.uniform_pm1((n, 19), seed=13))
+    f0[mask.reshape(-1) == 1] = 0.0
+    g = [1e-3, -4e-4, 3e-4]
+    fo = O.run(mask, f0, 6, 0.8, 3 / 16, g, 1, periodic=periodic)
+    idx = {tuple(c[i]): i for i in range(19)}
+    per = tuple(bool(periodic >> a & 1) for a in range(3))
+    br = Brute(nx, ny, nz, lambda x, y, z: bool(mask[z, y, x]), 0.8, 3 / 16, g, False, per)
+    st = {}
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                if not mask[z, y, x]:
+                    k = x + nx * (y + ny * z)
+                    st[(x, y, z)] = {v: f0[k, idx[v]] for v in velocities()}
+    for _ in range(6):
+        st = br.step(st)
+    fb = np.zeros_like(fo)
+    for (x, y, z), d in st.items():
+        for v, val in d.items():
+            fb[x + nx * (y + ny * z), idx[v]] = val
+    assert np.abs(fo - fb).max() <= 1e-15
+    # the faces matter: the fully periodic run differs
+    if periodic != 7:
+        assert np.abs(O.run(mask, f0, 6, 0.8, 3 / 16, g, 1) - fo).max() > 1e-6
+
+
+@pytest.mark.parametrize("periodic", sorted(BITS))
+def test_wall_faces_equal_solid_layers(periodic):
+    """A box whose non-wrapping faces are walls evolves exactly like the same
+    box padded with a solid layer on each of those faces and wrapped on
+    every axis (half-way bounce-back: the reflection happens at the same
+    link, with the same arithmetic)."""
+    nx, ny, nz = 5, 4, 6
+    mask = I.random_solid_mask(nx, ny, nz, seed=3, fraction=0.1)
+    pad = [(0 if periodic >> a & 1 else 1) for a in (2, 1, 0)]  # (z, y, x) order
+    big = np.pad(mask, [(p, p) for p in pad], constant_values=1)
+    c, w, _ = O.table()
+    f0 = w[None, :] * (1 + 0.02 * I.uniform_pm1((mask.size, 19), seed=17))
+    f0[mask.reshape(-1) == 1] = 0.0
+    fb0 = np.zeros((big.size, 19))
+    sl = tuple(slice(p, p + s) for p, s in zip(pad, mask.shape))
+    fb0.reshape(big.shape + (19,))[sl] = f0.reshape(mask.shape + (19,))
+    g = [2e-4, 1e-4, -1e-4]
+    a = O.run(mask, f0, 15, 0.9, 3 / 16, g, 1, periodic=periodic)
+    b = O.run(big, fb0, 15, 0.9, 3 / 16, g, 1)
+    assert np.array_equal(a.reshape(mask.shape + (19,)), b.reshape(big.shape + (19,))[sl])
+
+
+@pytest.mark.parametrize("magic", [3 / 16, 1 / 4])
+def test_wall_faces_slab_closed_form(magic):
+    """The slab of Sect. 2.1 without plate layers: z does not wrap, so the
+    plates are the z faces of an all-fluid box, half a link outside the
+    outer layers.  The steady state is the closed form of the slab with
+    plate layers (TRT slip included), restricted to its fluid layers."""
+    nz, tp, gx = 8, 0.8, 1e-5
+    mask = np.zeros((nz, 3, 3), dtype=np.uint8)
+    f = O.rest_state(mask, 1)
+    f, _, r = O.run_to_steady(mask, f, tp, magic, [gx, 0, 0], 1, 1e-12, 200,
+                              max_steps=20000, periodic=0b011)
+    assert r < 1e-12
+    ux = O.macroscopic(mask, f, [gx, 0, 0])[1].reshape(nz, 3, 3, 3)[..., 0]
+    ref = O.slab_profile(nz + 2, tp, magic, gx)[1:-1]
+    assert np.abs(ux - ref[:, None, None]).max() <= 1e-11 * ref.max()
+
+
+def test_wall_faces_fullway():
+    """Full-way bounce-back keeps reflected populations in solid nodes, so a
+    wall face needs solid boundary layers: with them the run equals the
+    wrapped one; with a fluid node on such a face the oracle refuses."""
+    mask = I.slab_mask(3, 4, 7)
+    c, w, _ = O.table()
+    f0 = w[None, :] * (1 + 0.01 * I.uniform_pm1((mask.size, 19), seed=19))
+    g = [1e-4, 0, 0]
+    a = O.run(mask, f0, 9, 0.8, 3 / 16, g, 0, periodic=0b011)
+    assert np.array_equal(a, O.run(mask, f0, 9, 0.8, 3 / 16, g, 0))
+    with pytest.raises(ValueError):
+        O.run(mask, f0, 1, 0.8, 3 / 16, g, 0, periodic=0b101)
