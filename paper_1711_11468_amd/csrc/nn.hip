@@ -1,6 +1,8 @@
 // nn.hip - BF16 MFMA kernels of the learned warm start (ABI: include/lbm_nn.h).
 //
-// Convolutions are implicit GEMMs on v_mfma_f32_16x16x16_bf16: one wavefront
+// Convolutions are implicit GEMMs.  The stride-1 3x3x3 forward on tileable
+// grids runs through LDS on v_mfma_f32_16x16x32_bf16 (k_conv_fwd_lds below);
+// the other forms use v_mfma_f32_16x16x16_bf16, where one wavefront
 // owns a 16 x 16 tile of the (voxel x channel) output and walks the K
 // dimension (taps x input-channel chunks of 16).  Operand layout of the
 // instruction (64 lanes, l = lane): A[i][k] lives in lane i + 16*(k/4),
@@ -214,6 +216,179 @@ k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
         if (g.act) v = v > 0.f ? v : v * g.slope;
         if (OUTF32) ((float*)y)[vox * g.cstore + co] = v;
         else ((uint16_t*)y)[vox * g.cstore + co] = f2bf(v);
+      }
+    }
+  }
+}
+
+// ---- forward through LDS, gfx950 16x16x32 MFMA ------------------------------
+// Stride-1 3x3x3 convolution on grids whose W is a multiple of 16 and whose
+// D and H are multiples of 4.  A workgroup computes a 16 x 4 x 4 (x, y, z)
+// block of output voxels for every output channel.  Per chunk of 32 input
+// channels (16 for a remainder) it stages the 18 x 6 x 6 input voxels of the
+// block and its periodic halo in LDS once; the four wavefronts (one z plane
+// each, four 16-voxel rows) then run all 27 taps from LDS, 32 channels of K
+// per v_mfma_f32_16x16x32_bf16 (a 16-channel chunk puts two taps side by
+// side).
+// Operand layout of the instruction (l = lane, e = 0..7 / 0..3): A[i][k] in
+// lane i + 16*(k/8), element k%8; B[k][j] in lane j + 16*(k/8), element k%8;
+// D[i][j] in lane j + 16*(i/4), element i%4.  A holds the weights (i: output
+// channel), B the input (j: voxel of the row), so a lane ends with four
+// consecutive output channels of one voxel and stores them at once.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+constexpr int kLdsTX = 16, kLdsTY = 4, kLdsTZ = 4;
+constexpr int kLdsHX = kLdsTX + 2, kLdsHY = kLdsTY + 2, kLdsHZ = kLdsTZ + 2;
+constexpr int kLdsHalo = kLdsHX * kLdsHY * kLdsHZ;  // 648 voxels
+constexpr int kLdsChunk = 32;                       // input channels per stage
+constexpr int kLdsPad = 8;                          // bf16 pad per staged voxel
+constexpr size_t kLdsBytes = (size_t)kLdsHalo * (kLdsChunk + kLdsPad) * 2;
+// Workgroups the LDS forward aims for: output-channel blocks are split over
+// workgroups until a launch has at least this many (one per compute unit).
+constexpr int64_t kLdsMinGroups = 256;
+
+// Moves a 16-byte fragment one voxel along the 16 lanes of each row of the
+// wavefront: lane r takes lane r - 1 (up = false) or r + 1 (up = true); the
+// lane with no neighbour in its row takes `edge`.
+__device__ __forceinline__ bf8 row_shift8(bf8 edge, bf8 v, bool up) {
+  union U { bf8 f; int i[4]; };
+  U e, a, r;
+  e.f = edge;
+  a.f = v;
+#pragma unroll
+  for (int h = 0; h < 4; ++h)
+    r.i[h] = up ? __builtin_amdgcn_update_dpp(e.i[h], a.i[h], 0x101, 0xF, 0xF, false)   // row_shl:1
+                : __builtin_amdgcn_update_dpp(e.i[h], a.i[h], 0x111, 0xF, 0xF, false);  // row_shr:1
+  return r.f;
+}
+
+// One staged chunk of CK (16 or 32) input channels, all 27 taps.  The three
+// x taps of a (z, y) pair read the same 16 staged voxels shifted by one, so
+// per (z, y) pair and row one fragment is read (the voxels x0 .. x0 + 15)
+// with the two halo voxels of the row, each read by all 16 lanes of a row
+// at one address (an LDS broadcast); the x - 1 and x + 1 operands are lane
+// shifts of it.  CK = 32: lanes take channels 8 * (lane / 16) .. + 7 of one
+// tap.  CK = 16: lanes 0-31 and 32-63 take two different (z, y) pairs
+// (half = lane / 32) with the same x tap; the ninth pair runs with zero
+// weights in the upper half.  srow points at the lane's channel group in the
+// staged voxel (x = -1, y = -1, z = wave - 1); wbase at the lane's output
+// channel and channel group in tap 0.
+template <int CK, int NB>
+__device__ __forceinline__ void conv_lds_chunk(const uint16_t* __restrict__ srow,
+                                               const uint16_t* __restrict__ wbase, int row, int half,
+                                               int ci, int64_t tap_stride, f4 (&acc)[kLdsTY][NB]) {
+  constexpr int VS = CK + kLdsPad;
+  constexpr int NPAIR = CK == 32 ? 9 : 5;  // instructions per x tap
+  const bf8 zero8 = {};
+#pragma unroll
+  for (int p = 0; p < NPAIR; ++p) {
+    // the (z, y) pair of this lane's half
+    const int ca = CK == 32 ? p : 2 * p;
+    const bool pad = CK == 16 && 2 * p + 1 > 8;
+    const int cb = CK == 32 ? p : (pad ? ca : 2 * p + 1);
+    const int c = half ? cb : ca;
+    const int zy = ((c / 3) * kLdsHY + c % 3) * kLdsHX * VS;  // staged offset of the pair
+    bf8 wf[3][NB];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        wf[dx][nb] = *(const bf8*)(wbase + (int64_t)(3 * c + dx) * tap_stride + (int64_t)nb * 16 * ci);
+        if (pad && half) wf[dx][nb] = zero8;
+      }
+#pragma unroll
+    for (int m = 0; m < kLdsTY; ++m) {
+      const uint16_t* rp = srow + zy + m * kLdsHX * VS;
+      const bf8 mid = *(const bf8*)(rp + (row + 1) * VS);
+      const bf8 lo = *(const bf8*)(rp);                    // staged x = 0, all lanes of the row
+      const bf8 hi = *(const bf8*)(rp + (kLdsHX - 1) * VS);  // staged x = 17
+      const bf8 bm = row_shift8(lo, mid, false);           // voxels x - 1
+      const bf8 bp = row_shift8(hi, mid, true);            // voxels x + 1
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[0][nb], bm, acc[m][nb], 0, 0, 0);
+        acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[1][nb], mid, acc[m][nb], 0, 0, 0);
+        acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[2][nb], bp, acc[m][nb], 0, 0, 0);
+      }
+    }
+  }
+}
+
+template <int NB, bool OUTF32>
+__global__ void __launch_bounds__(256)
+k_conv_fwd_lds(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
+               const float* __restrict__ bias, void* __restrict__ y, int64_t n_tiles, int parts, Geom g) {
+  extern __shared__ __align__(16) uint16_t stage[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, kq = lane >> 4, half = kq >> 1;
+  // workgroup -> (block, part): the `parts` workgroups of a block each take
+  // NB of its 16-channel output blocks (consecutive, so on the same XCD)
+  int64_t t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= n_tiles * parts) return;
+  const int co0 = (int)(t % parts) * NB * 16;
+  t /= parts;
+  const int tx = g.W / kLdsTX, ty = g.H / kLdsTY, tz = g.D / kLdsTZ;
+  const int x0 = (int)(t % tx) * kLdsTX;
+  t /= tx;
+  const int y0 = (int)(t % ty) * kLdsTY;
+  t /= ty;
+  const int z0 = (int)(t % tz) * kLdsTZ;
+  const int b = (int)(t / tz);
+  f4 acc[kLdsTY][NB];
+#pragma unroll
+  for (int m = 0; m < kLdsTY; ++m)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f4{0.f, 0.f, 0.f, 0.f};
+  const int64_t tap_stride = (int64_t)g.co * g.ci;
+  const int vz = wave * kLdsHY * kLdsHX;  // staged voxel (x = -1, y = -1) of the wave's z plane
+  for (int c0 = 0; c0 < g.ci; c0 += kLdsChunk) {
+    const int ck = g.ci - c0 < kLdsChunk ? g.ci - c0 : kLdsChunk;  // 32 or 16
+    const int vs = ck + kLdsPad;                                    // staged voxel stride
+    const int parts = ck / 8;                                       // 16-byte pieces per voxel
+    __syncthreads();  // the previous chunk has been read
+    for (int p = threadIdx.x; p < kLdsHalo * parts; p += 256) {
+      const int v = p / parts, part = p - v * parts;
+      const int hx = v % kLdsHX, hy = (v / kLdsHX) % kLdsHY, hz = v / (kLdsHX * kLdsHY);
+      const int gx = wrapi(x0 + hx - 1, g.W), gy = wrapi(y0 + hy - 1, g.H), gz = wrapi(z0 + hz - 1, g.D);
+      const int64_t gv = (((int64_t)b * g.D + gz) * g.H + gy) * g.W + gx;
+      *(uint4*)(stage + v * vs + part * 8) = *(const uint4*)(x + gv * g.ci + c0 + part * 8);
+    }
+    __syncthreads();
+    // channel group of the lane: 8 * (lane / 16) of a 32-channel chunk, or
+    // 8 * (lane / 16 % 2) of a 16-channel chunk (the halves take two taps)
+    const int grp = ck == 32 ? 8 * kq : 8 * (kq & 1);
+    const uint16_t* wbase = w + (int64_t)(co0 + row) * g.ci + c0 + grp;
+    if (ck == 32)
+      conv_lds_chunk<32, NB>(stage + vz * (32 + kLdsPad) + grp, wbase, row, half, g.ci, tap_stride, acc);
+    else
+      conv_lds_chunk<16, NB>(stage + vz * (16 + kLdsPad) + grp, wbase, row, half, g.ci, tap_stride, acc);
+  }
+#pragma unroll
+  for (int m = 0; m < kLdsTY; ++m) {
+    const int64_t vox = (((int64_t)b * g.Do + z0 + wave) * g.Ho + y0 + m) * g.Wo + x0 + row;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int cb = co0 + nb * 16 + 4 * kq;  // first of the lane's four channels
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        v[e] = acc[m][nb][e] + (bias ? bias[cb + e] : 0.f);
+        if (g.act) v[e] = v[e] > 0.f ? v[e] : v[e] * g.slope;
+      }
+      if ((g.cstore & 3) == 0 && cb + 4 <= g.cstore) {  // aligned four-channel store
+        if (OUTF32) {
+          *(f4*)((float*)y + vox * g.cstore + cb) = f4{v[0], v[1], v[2], v[3]};
+        } else {
+          const uint2 pk = {(uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
+                            (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16)};
+          *(uint2*)((uint16_t*)y + vox * g.cstore + cb) = pk;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (cb + e >= g.cstore) continue;
+          if (OUTF32) ((float*)y)[vox * g.cstore + cb + e] = v[e];
+          else ((uint16_t*)y)[vox * g.cstore + cb + e] = f2bf(v[e]);
+        }
       }
     }
   }
@@ -884,6 +1059,28 @@ static void launch_fwd_nb(int nb, const uint16_t* x, const uint16_t* w, const fl
   }
 }
 
+// The LDS forward for stride-1 3x3x3 layers on grids it tiles; false if
+// the layer does not qualify (then the per-wavefront kernel runs).
+template <bool F32>
+static bool launch_fwd_lds(int nb, const uint16_t* x, const uint16_t* w, const float* bias, void* y,
+                           const Geom& g, hipStream_t s) {
+  if (g.W % kLdsTX || g.H % kLdsTY || g.D % kLdsTZ) return false;
+  const int64_t n_tiles = (int64_t)g.B * (g.D / kLdsTZ) * (g.H / kLdsTY) * (g.W / kLdsTX);
+  // output blocks per workgroup: the most (4, 2 or 1) that divides nb and
+  // still gives kLdsMinGroups workgroups, else 1
+  int per = 1;
+  for (int c = 4; c > 1; c /= 2)
+    if (nb % c == 0 && n_tiles * (nb / c) >= kLdsMinGroups) { per = c; break; }
+  const int parts = nb / per;
+  const dim3 grid(pad_xcd((unsigned)(n_tiles * parts))), block(256);
+  switch (per) {
+    case 1: hipLaunchKernelGGL((k_conv_fwd_lds<1, F32>), grid, block, kLdsBytes, s, x, w, bias, y, n_tiles, parts, g); break;
+    case 2: hipLaunchKernelGGL((k_conv_fwd_lds<2, F32>), grid, block, kLdsBytes, s, x, w, bias, y, n_tiles, parts, g); break;
+    default: hipLaunchKernelGGL((k_conv_fwd_lds<4, F32>), grid, block, kLdsBytes, s, x, w, bias, y, n_tiles, parts, g); break;
+  }
+  return true;
+}
+
 template <int STRIDE, int TAPS, int MT>
 static void launch_dgrad_mt(int nb, const uint16_t* dy, const uint16_t* wt, float* dx, int acc,
                             const Geom& g, hipStream_t s) {
@@ -949,6 +1146,11 @@ int nn_conv3d_fwd(const nn_conv_desc* d, const uint16_t* x, const uint16_t* w, c
   const Geom g = make_geom(d);
   hipStream_t s = (hipStream_t)stream;
   const int nb = d->c_out / 16;
+  if (d->taps == 27 && d->stride == 1 &&
+      (d->out_f32 ? launch_fwd_lds<true>(nb, x, w, bias, y, g, s) : launch_fwd_lds<false>(nb, x, w, bias, y, g, s))) {
+    NN_HIP_CHECK("conv fwd");
+    return 0;
+  }
   if (d->taps == 1) {
     if (d->stride != 1) { set_error("1x1x1 convolution has stride 1"); return -1; }
     if (d->out_f32) launch_fwd_nb<1, 1, true>(nb, x, w, bias, y, g, s);

@@ -36,7 +36,17 @@ CASES = [  # (batch, n, c_in, c_out, stride, taps)
 ]
 
 
-@pytest.mark.parametrize("case", CASES)
+# grids the LDS forward tiles (W % 16, H % 4, D % 4): 32-channel chunks, a
+# 32 + 16 split, three and four chunks, one, two and four 16-channel output
+# blocks per workgroup, and output channels split over workgroups on small
+# grids (16^3 with 64 outputs: four workgroups per block)
+FWD_CASES = CASES + [
+    (1, 32, 32, 64, 1, 27), (1, 32, 48, 16, 1, 27), (1, 32, 96, 32, 1, 27),
+    (1, 32, 128, 64, 1, 27), (2, 32, 64, 32, 1, 27), (1, 16, 64, 64, 1, 27),
+]
+
+
+@pytest.mark.parametrize("case", FWD_CASES)
 def test_conv_forward(NN, case):
     B, n, ci, co, s, taps = case
     x = _bf((B, n, n, n, ci), 1)
@@ -50,6 +60,24 @@ def test_conv_forward(NN, case):
         d = NN.desc(B, n, n, n, ci, co, stride=s, taps=taps, act=act, slope=0.1, out_f32=out_f32)
         NN.conv_fwd(d, x.to(dev), w.to(dev), b.to(dev), y)
         ref = R.conv(x.double(), w.double(), b.double(), stride=s, taps=taps, act=act)
+        got = y.cpu().double().reshape(ref.shape)
+        assert rel(got, ref) <= (2e-6 if out_f32 else 8e-3), (out_f32, rel(got, ref))
+
+
+@pytest.mark.parametrize("n,ci,co,c_store", [(32, 16, 16, 3), (32, 32, 32, 8), (8, 16, 32, 5)])
+def test_conv_forward_stored_channels(NN, n, ci, co, c_store):
+    """Only the first c_store output channels are written, in a tensor of
+    c_store channels (the LDS forward and the per-wavefront kernel)."""
+    x = _bf((1, n, n, n, ci), 7)
+    w = _bf((27, co, ci), 8, (2.0 / (27 * ci)) ** 0.5)
+    b = torch.randn(co, generator=torch.Generator().manual_seed(9)) * 0.1
+    dev = torch.device("cuda")
+    for out_f32 in (True, False):
+        y = torch.empty(n ** 3 * c_store, dtype=torch.float32 if out_f32 else torch.bfloat16,
+                        device=dev)
+        d = NN.desc(1, n, n, n, ci, co, c_store=c_store, act=True, slope=0.1, out_f32=out_f32)
+        NN.conv_fwd(d, x.to(dev), w.to(dev), b.to(dev), y)
+        ref = R.conv(x.double(), w.double(), b.double(), stride=1, taps=27, act=True)[..., :c_store]
         got = y.cpu().double().reshape(ref.shape)
         assert rel(got, ref) <= (2e-6 if out_f32 else 8e-3), (out_f32, rel(got, ref))
 
