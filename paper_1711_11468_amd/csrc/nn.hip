@@ -241,7 +241,6 @@ constexpr int kLdsHX = kLdsTX + 2, kLdsHY = kLdsTY + 2, kLdsHZ = kLdsTZ + 2;
 constexpr int kLdsHalo = kLdsHX * kLdsHY * kLdsHZ;  // 648 voxels
 constexpr int kLdsChunk = 32;                       // input channels per stage
 constexpr int kLdsPad = 8;                          // bf16 pad per staged voxel
-constexpr size_t kLdsBytes = (size_t)kLdsHalo * (kLdsChunk + kLdsPad) * 2;
 // Workgroups the LDS forward aims for: output-channel blocks are split over
 // workgroups until a launch has at least this many (one per compute unit).
 constexpr int64_t kLdsMinGroups = 256;
@@ -862,32 +861,71 @@ __global__ void k_prepare_input(const uint8_t* __restrict__ mask, uint16_t* __re
 // edge n, relaxed from 0 on solids and dmax on fluid; one sweep moves the
 // front by one voxel, so after ceil(dmax) sweeps every distance below dmax
 // has its final value.
+// One sweep, as a thread per (x, y) column and run of RUN planes in z
+// (consecutive lanes take consecutive x, so every load is coalesced): the
+// thread keeps the 3 x 3 source values around its column in the planes
+// z - 1, z and z + 1 in registers and slides them along z, loading nine new
+// values per voxel instead of 26.  Indices are 32-bit (the caller checks
+// that the cubes hold fewer than 2^31 voxels).
+template <int RUN>
 __global__ void k_dist_relax(const uint8_t* __restrict__ mask, const float* __restrict__ src,
-                             float* __restrict__ dst, int n, int64_t total, float dmax) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= total) return;
-  if (mask[e] != 0) { dst[e] = 0.f; return; }
-  const int64_t n3 = (int64_t)n * n * n;
-  const int64_t base = e - e % n3;
-  const int r = (int)(e - base);
-  const int x = r % n, y = (r / n) % n, z = r / (n * n);
-  float best = src[e];
+                             float* __restrict__ dst, int n, int n_threads, float dmax) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_threads) return;
+  const int x = t % n;
+  int r = t / n;
+  const int y = r % n;
+  r /= n;
+  const int runs = n / RUN;
+  const int z0 = (r % runs) * RUN;
+  const int cube = (r / runs) * n * n * n;
+  const int n2 = n * n;
+  auto wrap = [n](int v) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+  // in-plane offsets of the 3 x 3 neighbourhood, j = 3 * (dy + 1) + dx + 1
+  int off[9];
 #pragma unroll
-  for (int dz = -1; dz <= 1; ++dz)
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) off[3 * (dy + 1) + dx + 1] = wrap(y + dy) * n + wrap(x + dx);
+  // step length to the neighbour at (dx, dy, dz)
+  auto step = [](int dx, int dy, int dz) {
+    const int k = dx * dx + dy * dy + dz * dz;
+    return k == 1 ? 1.f : (k == 2 ? 1.41421356f : 1.73205081f);
+  };
+  float pm[9], pc[9], pp[9];
+  {
+    const int bm = cube + wrap(z0 - 1) * n2, bc = cube + z0 * n2, bp = cube + wrap(z0 + 1) * n2;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      pm[j] = src[bm + off[j]];
+      pc[j] = src[bc + off[j]];
+      pp[j] = src[bp + off[j]];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RUN; ++i) {
+    const int e = cube + (z0 + i) * n2 + off[4];
+    float best = pc[4];
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
-        const int k = dx * dx + dy * dy + dz * dz;
-        if (k == 0) continue;
-        const float w = k == 1 ? 1.f : (k == 2 ? 1.41421356f : 1.73205081f);
-        int xx = x + dx, yy = y + dy, zz = z + dz;
-        xx = xx < 0 ? xx + n : (xx >= n ? xx - n : xx);
-        yy = yy < 0 ? yy + n : (yy >= n ? yy - n : yy);
-        zz = zz < 0 ? zz + n : (zz >= n ? zz - n : zz);
-        best = fminf(best, src[base + xx + (int64_t)n * (yy + (int64_t)n * zz)] + w);
+        const int j = 3 * (dy + 1) + dx + 1;
+        best = fminf(best, pm[j] + step(dx, dy, -1));
+        if (j != 4) best = fminf(best, pc[j] + step(dx, dy, 0));
+        best = fminf(best, pp[j] + step(dx, dy, 1));
       }
-  dst[e] = fminf(best, dmax);
+    dst[e] = mask[e] != 0 ? 0.f : fminf(best, dmax);
+    if (i + 1 < RUN) {
+      const int bn = cube + wrap(z0 + i + 2) * n2;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        pm[j] = pc[j];
+        pc[j] = pp[j];
+        pp[j] = src[bn + off[j]];
+      }
+    }
+  }
 }
 
 __global__ void k_dist_init(const uint8_t* __restrict__ mask, float* __restrict__ d, int64_t total,
@@ -897,6 +935,25 @@ __global__ void k_dist_init(const uint8_t* __restrict__ mask, float* __restrict_
 }
 
 // Input channels: 0 solid, 1 fluid, 2 d/dmax, 3 (d/dmax)^2, the rest zero.
+// One thread per voxel and group of 8 channels (one 16-byte store), for
+// channel counts that are multiples of 8.
+__global__ void k_features8(const uint8_t* __restrict__ mask, const float* __restrict__ dist,
+                            uint16_t* __restrict__ x, int64_t total, int cpad, float dmax) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int groups = cpad / 8;
+  if (e >= total * groups) return;
+  const int64_t i = e / groups;
+  const int g = (int)(e - i * groups);
+  uint4 v = {0u, 0u, 0u, 0u};
+  if (g == 0) {
+    const bool solid = mask[i] != 0;
+    const float q = dist[i] / dmax;
+    v.x = (uint32_t)f2bf(solid ? 1.f : 0.f) | ((uint32_t)f2bf(solid ? 0.f : 1.f) << 16);
+    v.y = (uint32_t)f2bf(q) | ((uint32_t)f2bf(q * q) << 16);
+  }
+  *(uint4*)(x + i * cpad + 8 * g) = v;
+}
+
 __global__ void k_features(const uint8_t* __restrict__ mask, const float* __restrict__ dist,
                            uint16_t* __restrict__ x, int64_t total, int cpad, float dmax) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1073,10 +1130,13 @@ static bool launch_fwd_lds(int nb, const uint16_t* x, const uint16_t* w, const f
     if (nb % c == 0 && n_tiles * (nb / c) >= kLdsMinGroups) { per = c; break; }
   const int parts = nb / per;
   const dim3 grid(pad_xcd((unsigned)(n_tiles * parts))), block(256);
+  // LDS for the widest chunk of this layer (16-channel layers stage 24
+  // elements per voxel, which lets more workgroups share a compute unit)
+  const size_t lds = (size_t)kLdsHalo * ((g.ci < kLdsChunk ? g.ci : kLdsChunk) + kLdsPad) * 2;
   switch (per) {
-    case 1: hipLaunchKernelGGL((k_conv_fwd_lds<1, F32>), grid, block, kLdsBytes, s, x, w, bias, y, n_tiles, parts, g); break;
-    case 2: hipLaunchKernelGGL((k_conv_fwd_lds<2, F32>), grid, block, kLdsBytes, s, x, w, bias, y, n_tiles, parts, g); break;
-    default: hipLaunchKernelGGL((k_conv_fwd_lds<4, F32>), grid, block, kLdsBytes, s, x, w, bias, y, n_tiles, parts, g); break;
+    case 1: hipLaunchKernelGGL((k_conv_fwd_lds<1, F32>), grid, block, lds, s, x, w, bias, y, n_tiles, parts, g); break;
+    case 2: hipLaunchKernelGGL((k_conv_fwd_lds<2, F32>), grid, block, lds, s, x, w, bias, y, n_tiles, parts, g); break;
+    default: hipLaunchKernelGGL((k_conv_fwd_lds<4, F32>), grid, block, lds, s, x, w, bias, y, n_tiles, parts, g); break;
   }
   return true;
 }
@@ -1409,20 +1469,35 @@ int nn_prepare_input_dist(const uint8_t* mask, uint16_t* x, int32_t batch, int32
     return -1;
   }
   const int64_t total = (int64_t)batch * n * n * n;
+  if (total >= 0x7fffffffLL) {
+    set_error("more than 2^31 voxels");
+    return -1;
+  }
   hipStream_t s = (hipStream_t)stream;
   float* a = work;
   float* b = work + total;
   hipLaunchKernelGGL(k_dist_init, dim3(nblk(total, 256)), dim3(256), 0, s, mask, a, total, dmax);
   const int sweeps = (int)ceilf(dmax);
+  constexpr int kRun = 8;  // planes per thread when n allows
+  const bool runs = n % kRun == 0;
+  const int threads = (int)(runs ? total / kRun : total);
   for (int k = 0; k < sweeps; ++k) {
-    hipLaunchKernelGGL(k_dist_relax, dim3(nblk(total, 256)), dim3(256), 0, s, mask, a, b, n, total,
-                       dmax);
+    if (runs)
+      hipLaunchKernelGGL(k_dist_relax<kRun>, dim3(nblk(threads, 256)), dim3(256), 0, s, mask, a, b, n,
+                         threads, dmax);
+    else
+      hipLaunchKernelGGL(k_dist_relax<1>, dim3(nblk(threads, 256)), dim3(256), 0, s, mask, a, b, n,
+                         threads, dmax);
     float* t = a;
     a = b;
     b = t;
   }
-  hipLaunchKernelGGL(k_features, dim3(nblk(total * c_pad, 256)), dim3(256), 0, s, mask, a, x, total,
-                     c_pad, dmax);
+  if (c_pad % 8 == 0 && ((uintptr_t)x & 15) == 0)
+    hipLaunchKernelGGL(k_features8, dim3(nblk(total * (c_pad / 8), 256)), dim3(256), 0, s, mask, a, x,
+                       total, c_pad, dmax);
+  else
+    hipLaunchKernelGGL(k_features, dim3(nblk(total * c_pad, 256)), dim3(256), 0, s, mask, a, x, total,
+                       c_pad, dmax);
   NN_HIP_CHECK("prepare input with distance");
   return 0;
 }

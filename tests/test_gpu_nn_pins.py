@@ -114,7 +114,8 @@ def test_velocity_out_definition(NN):
     assert np.array_equal(u.cpu().numpy().reshape(3, n), want)
 
 
-def test_distance_features_closed_form(NN):
+@pytest.mark.parametrize("n", [16, 12, 48])
+def test_distance_features_closed_form(NN, n):
     """nn_prepare_input_dist around a single solid voxel of a periodic cube:
     the 26-neighbourhood chamfer distance to it has the closed form
     (a - b) + (b - c) sqrt 2 + c sqrt 3 for sorted offsets a >= b >= c
@@ -122,11 +123,14 @@ def test_distance_features_closed_form(NN):
     (d/dmax)^2 rounded to bf16 (within one bf16 ulp of the float64 value,
     since the kernel sums the steps in float32), channels 0/1 the solid and
     fluid indicators, the padding channels zero.  Two cubes in one batch,
-    the solid voxel at different places (the batch index does not leak)."""
+    the solid voxel at different places (the batch index does not leak).
+    Edges 16 and 48 take the kernel's runs of 8 planes per thread (two and
+    six runs per column), 12 the one-plane form; cpad 16 the 8-channel
+    stores, cpad 12 the one-channel ones."""
     dev = torch.device("cuda")
-    n, dmax, cpad = 16, 6.0, 16
+    dmax, cpad = 6.0, (12 if n == 12 else 16)
     mask = np.zeros((2, n, n, n), np.uint8)       # [b][z][y][x]
-    spots = [(3, 5, 7), (12, 0, 15)]              # (x, y, z)
+    spots = [(3, 5, 7), (n - 4, 0, n - 1)]        # (x, y, z)
     for b, (x, y, z) in enumerate(spots):
         mask[b, z, y, x] = 1
     x_t = torch.empty(2 * n ** 3 * cpad, dtype=torch.bfloat16, device=dev)
