@@ -176,7 +176,7 @@ def cnn_throughput(steps=10, which=("infer_128", "train_64x4")):
             if train:
                 net.train_step(mask, tgt, B, n, lr=1e-4)
             else:
-                net.forward(mask, B, n)
+                net.forward(mask, B, n, fuse_concat=True)  # as predict_velocity runs it
         for _ in range(3):
             once()
         torch.cuda.synchronize()

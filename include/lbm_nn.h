@@ -54,6 +54,19 @@ typedef struct {
 int nn_conv3d_fwd(const nn_conv_desc* d, const uint16_t* x, const uint16_t* w,
                   const float* bias, void* y, void* stream);
 
+/* nn_conv3d_fwd of the channel concatenation nn_up_concat would form, read
+ * straight from its two parts without forming it (the decoder's first
+ * layer at inference).  Input channels 0 .. c_coarse-1 are coarse[b, z/2,
+ * y/2, x/2] ([B][D/2][H/2][W/2][c_coarse] bf16), channels c_coarse ..
+ * c_in-1 are skip[b, z, y, x] ([B][D][H][W][c_in - c_coarse] bf16); (D, H,
+ * W) in d is the fine grid.  Stride 1 and 27 taps only; W a multiple of 16,
+ * H and D of 4; c_coarse a multiple of 8 below c_in.  Else returns -1 and
+ * nothing is launched; the result equals nn_up_concat followed by
+ * nn_conv3d_fwd bit for bit. */
+int nn_conv3d_fwd_upcat(const nn_conv_desc* d, const uint16_t* coarse, int32_t c_coarse,
+                        const uint16_t* skip, const uint16_t* w, const float* bias, void* y,
+                        void* stream);
+
 /* Data gradient: dx (+)= conv^T(dy, w), the gradient with respect to the
  * input of the convolution given dy, the gradient with respect to its
  * pre-activation output ([B][D/s][H/s][W/s][c_out] bf16).  dx: [B][D][H][W]

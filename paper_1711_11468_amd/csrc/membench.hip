@@ -87,10 +87,11 @@ k_streams(const double2* __restrict__ a, double2* __restrict__ b, int64_t n2, in
 
 // Workgroups of a persistent grid: 8 per compute unit of the device.
 static unsigned persistent_grid() {
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess)
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  return (unsigned)(8 * (cus > 0 ? cus : 256));
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;  // MI355X
+  return (unsigned)(8 * cus);
 }
 
 hipError_t launch_membench(int kind, const double* a, double* b, int64_t n, int64_t stride,

@@ -314,8 +314,9 @@ __device__ __forceinline__ void conv_lds_chunk(const uint16_t* __restrict__ srow
 
 template <int NB, bool OUTF32>
 __global__ void __launch_bounds__(256)
-k_conv_fwd_lds(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
-               const float* __restrict__ bias, void* __restrict__ y, int64_t n_tiles, int parts, Geom g) {
+k_conv_fwd_lds(const uint16_t* __restrict__ x, const uint16_t* __restrict__ xc, int c1,
+               const uint16_t* __restrict__ w, const float* __restrict__ bias, void* __restrict__ y,
+               int64_t n_tiles, int parts, Geom g) {
   extern __shared__ __align__(16) uint16_t stage[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 15, kq = lane >> 4, half = kq >> 1;
@@ -342,14 +343,22 @@ k_conv_fwd_lds(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
   for (int c0 = 0; c0 < g.ci; c0 += kLdsChunk) {
     const int ck = g.ci - c0 < kLdsChunk ? g.ci - c0 : kLdsChunk;  // 32 or 16
     const int vs = ck + kLdsPad;                                    // staged voxel stride
-    const int parts = ck / 8;                                       // 16-byte pieces per voxel
+    const int pieces = ck / 8;                                      // 16-byte pieces per voxel
     __syncthreads();  // the previous chunk has been read
-    for (int p = threadIdx.x; p < kLdsHalo * parts; p += 256) {
-      const int v = p / parts, part = p - v * parts;
+    for (int p = threadIdx.x; p < kLdsHalo * pieces; p += 256) {
+      const int v = p / pieces, piece = p - v * pieces;
       const int hx = v % kLdsHX, hy = (v / kLdsHX) % kLdsHY, hz = v / (kLdsHX * kLdsHY);
       const int gx = wrapi(x0 + hx - 1, g.W), gy = wrapi(y0 + hy - 1, g.H), gz = wrapi(z0 + hz - 1, g.D);
       const int64_t gv = (((int64_t)b * g.D + gz) * g.H + gy) * g.W + gx;
-      *(uint4*)(stage + v * vs + part * 8) = *(const uint4*)(x + gv * g.ci + c0 + part * 8);
+      // channels below c1 come from the coarse tensor, up-sampled by taking
+      // the coarse voxel (x / 2, y / 2, z / 2); the rest from x, which then
+      // holds g.ci - c1 channels (c1 = 0: x is the whole input)
+      const int ch = c0 + piece * 8;
+      const bool coarse = ch < c1;
+      const int64_t cv = (((int64_t)b * (g.D >> 1) + (gz >> 1)) * (g.H >> 1) + (gy >> 1)) * (g.W >> 1) + (gx >> 1);
+      const int64_t off = coarse ? cv * c1 + ch : gv * (g.ci - c1) + (ch - c1);
+      const uint16_t* base = coarse ? xc : x;
+      *(uint4*)(stage + v * vs + piece * 8) = *(const uint4*)(base + off);
     }
     __syncthreads();
     // channel group of the lane: 8 * (lane / 16) of a 32-channel chunk, or
@@ -1119,8 +1128,8 @@ static void launch_fwd_nb(int nb, const uint16_t* x, const uint16_t* w, const fl
 // The LDS forward for stride-1 3x3x3 layers on grids it tiles; false if
 // the layer does not qualify (then the per-wavefront kernel runs).
 template <bool F32>
-static bool launch_fwd_lds(int nb, const uint16_t* x, const uint16_t* w, const float* bias, void* y,
-                           const Geom& g, hipStream_t s) {
+static bool launch_fwd_lds(int nb, const uint16_t* x, const uint16_t* xc, int c1, const uint16_t* w,
+                           const float* bias, void* y, const Geom& g, hipStream_t s) {
   if (g.W % kLdsTX || g.H % kLdsTY || g.D % kLdsTZ) return false;
   const int64_t n_tiles = (int64_t)g.B * (g.D / kLdsTZ) * (g.H / kLdsTY) * (g.W / kLdsTX);
   // output blocks per workgroup: the most (4, 2 or 1) that divides nb and
@@ -1134,9 +1143,9 @@ static bool launch_fwd_lds(int nb, const uint16_t* x, const uint16_t* w, const f
   // elements per voxel, which lets more workgroups share a compute unit)
   const size_t lds = (size_t)kLdsHalo * ((g.ci < kLdsChunk ? g.ci : kLdsChunk) + kLdsPad) * 2;
   switch (per) {
-    case 1: hipLaunchKernelGGL((k_conv_fwd_lds<1, F32>), grid, block, lds, s, x, w, bias, y, n_tiles, parts, g); break;
-    case 2: hipLaunchKernelGGL((k_conv_fwd_lds<2, F32>), grid, block, lds, s, x, w, bias, y, n_tiles, parts, g); break;
-    default: hipLaunchKernelGGL((k_conv_fwd_lds<4, F32>), grid, block, lds, s, x, w, bias, y, n_tiles, parts, g); break;
+    case 1: hipLaunchKernelGGL((k_conv_fwd_lds<1, F32>), grid, block, lds, s, x, xc, c1, w, bias, y, n_tiles, parts, g); break;
+    case 2: hipLaunchKernelGGL((k_conv_fwd_lds<2, F32>), grid, block, lds, s, x, xc, c1, w, bias, y, n_tiles, parts, g); break;
+    default: hipLaunchKernelGGL((k_conv_fwd_lds<4, F32>), grid, block, lds, s, x, xc, c1, w, bias, y, n_tiles, parts, g); break;
   }
   return true;
 }
@@ -1207,7 +1216,8 @@ int nn_conv3d_fwd(const nn_conv_desc* d, const uint16_t* x, const uint16_t* w, c
   hipStream_t s = (hipStream_t)stream;
   const int nb = d->c_out / 16;
   if (d->taps == 27 && d->stride == 1 &&
-      (d->out_f32 ? launch_fwd_lds<true>(nb, x, w, bias, y, g, s) : launch_fwd_lds<false>(nb, x, w, bias, y, g, s))) {
+      (d->out_f32 ? launch_fwd_lds<true>(nb, x, nullptr, 0, w, bias, y, g, s)
+                  : launch_fwd_lds<false>(nb, x, nullptr, 0, w, bias, y, g, s))) {
     NN_HIP_CHECK("conv fwd");
     return 0;
   }
@@ -1223,6 +1233,29 @@ int nn_conv3d_fwd(const nn_conv_desc* d, const uint16_t* x, const uint16_t* w, c
     else launch_fwd_nb<2, 27, false>(nb, x, w, bias, y, g, s);
   }
   NN_HIP_CHECK("conv fwd");
+  return 0;
+}
+
+int nn_conv3d_fwd_upcat(const nn_conv_desc* d, const uint16_t* coarse, int32_t c_coarse,
+                        const uint16_t* skip, const uint16_t* w, const float* bias, void* y, void* stream) {
+  if (check_desc(d)) return -1;
+  if (!coarse || !skip || !w || !y) { set_error("null tensor"); return -1; }
+  if (d->stride != 1 || d->taps != 27) { set_error("the fused up-sample/concat needs a stride-1 3x3x3 layer"); return -1; }
+  if (c_coarse < 8 || c_coarse % 8 || c_coarse >= d->c_in) {
+    set_error("c_coarse must be a multiple of 8 below c_in");
+    return -1;
+  }
+  if (d->d % 2 || d->h % 2 || d->w % 2) { set_error("the fine grid must have even sizes"); return -1; }
+  const Geom g = make_geom(d);
+  hipStream_t s = (hipStream_t)stream;
+  const int nb = d->c_out / 16;
+  const bool ok = d->out_f32 ? launch_fwd_lds<true>(nb, skip, coarse, c_coarse, w, bias, y, g, s)
+                             : launch_fwd_lds<false>(nb, skip, coarse, c_coarse, w, bias, y, g, s);
+  if (!ok) {
+    set_error("the fused up-sample/concat needs w %% 16, h %% 4 and d %% 4 == 0");
+    return -1;
+  }
+  NN_HIP_CHECK("conv fwd upcat");
   return 0;
 }
 

@@ -8,7 +8,7 @@ import ctypes
 
 from . import lbm
 
-NN_EXPORTED = ["nn_conv3d_fwd", "nn_conv3d_dgrad", "nn_conv3d_wgrad", "nn_conv3d_wgrad_workspace",
+NN_EXPORTED = ["nn_conv3d_fwd", "nn_conv3d_fwd_upcat", "nn_conv3d_dgrad", "nn_conv3d_wgrad", "nn_conv3d_wgrad_workspace",
                "nn_lrelu_bwd", "nn_up_concat", "nn_split_down", "nn_masked_mse",
                "nn_masked_mse_noalloc", "nn_adam_step", "nn_prepare_input", "nn_prepare_input_dist",
                "nn_velocity_labels", "nn_velocity_out",
@@ -37,6 +37,7 @@ def _lib():
         f64 = ctypes.c_double
         sig = {
             "nn_conv3d_fwd": [D, vp, vp, vp, vp, vp],
+            "nn_conv3d_fwd_upcat": [D, vp, i32, vp, vp, vp, vp, vp],
             "nn_conv3d_dgrad": [D, vp, vp, vp, vp, i32, vp],
             "nn_conv3d_wgrad": [D, vp, vp, vp, vp, vp, vp],
             "nn_conv3d_wgrad_workspace": [D],
@@ -88,6 +89,12 @@ def desc(batch, d, h, w, c_in, c_out, c_store=None, stride=1, taps=27, act=True,
 def conv_fwd(dsc, x, w, bias, y, stream=None):
     _check(_lib().nn_conv3d_fwd(ctypes.byref(dsc), _p(x), _p(w), _p(bias), _p(y), _s(stream)),
            "nn_conv3d_fwd")
+
+
+def conv_fwd_upcat(dsc, coarse, c_coarse, skip, w, bias, y, stream=None):
+    """conv_fwd of up_concat(coarse, skip) without forming the concatenation."""
+    _check(_lib().nn_conv3d_fwd_upcat(ctypes.byref(dsc), _p(coarse), int(c_coarse), _p(skip), _p(w),
+                                      _p(bias), _p(y), _s(stream)), "nn_conv3d_fwd_upcat")
 
 
 def conv_dgrad(dsc, dy, w, w_t, dx, accumulate=False, stream=None):

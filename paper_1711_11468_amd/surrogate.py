@@ -194,9 +194,12 @@ class UNet:
         return 3 * fwd - first if train else fwd
 
     # -- forward ----------------------------------------------------------------
-    def forward(self, mask_u8, batch, n):
+    def forward(self, mask_u8, batch, n, fuse_concat=False):
         """mask_u8: device uint8 [batch*n^3]; returns the float32 output
-        [batch*n^3][3] (normalised units)."""
+        [batch*n^3][3] (normalised units).  fuse_concat: the decoder's first
+        layers read the up-sampled coarse tensor and the skip tensor directly
+        instead of their concatenation (inference; the backward pass needs
+        the concatenations, so training keeps them)."""
         assert n % 16 == 0, "grid edge must be a multiple of 16"
         b = self._buffers(batch, n)
         A = b["a"]
@@ -213,12 +216,19 @@ class UNet:
         conv("d1", A["e0"], A["d1"]); conv("e1a", A["d1"], A["e1a"]); conv("e1", A["e1a"], A["e1"])
         conv("d2", A["e1"], A["d2"]); conv("e2a", A["d2"], A["e2a"]); conv("e2", A["e2a"], A["e2"])
         conv("d3", A["e2"], A["d3"]); conv("e3a", A["d3"], A["e3a"]); conv("e3", A["e3a"], A["e3"])
-        nn.up_concat(A["e3"], A["e2"], A["c2"], batch, S[2], S[2], S[2], CH[3], CH[2])
-        conv("u2a", A["c2"], A["u2a"]); conv("u2", A["u2a"], A["u2"])
-        nn.up_concat(A["u2"], A["e1"], A["c1"], batch, S[1], S[1], S[1], CH[2], CH[1])
-        conv("u1a", A["c1"], A["u1a"]); conv("u1", A["u1a"], A["u1"])
-        nn.up_concat(A["u1"], A["e0"], A["c0"], batch, S[0], S[0], S[0], CH[1], CH[0])
-        conv("u0a", A["c0"], A["u0a"]); conv("u0", A["u0a"], A["u0"])
+        def upcat_conv(name, coarse, c_coarse, skip, cat, lvl, c_skip):
+            lyr = L[name]
+            dsc = lyr.desc(batch, S[lvl])
+            if fuse_concat and S[lvl] % 16 == 0:
+                nn.conv_fwd_upcat(dsc, coarse, c_coarse, skip, self.p[name]["w16"], self.p[name]["b"],
+                                  A[name])
+            else:
+                nn.up_concat(coarse, skip, cat, batch, S[lvl], S[lvl], S[lvl], c_coarse, c_skip)
+                conv(name, cat, A[name])
+
+        upcat_conv("u2a", A["e3"], CH[3], A["e2"], A["c2"], 2, CH[2]); conv("u2", A["u2a"], A["u2"])
+        upcat_conv("u1a", A["u2"], CH[2], A["e1"], A["c1"], 1, CH[1]); conv("u1", A["u1a"], A["u1"])
+        upcat_conv("u0a", A["u1"], CH[1], A["e0"], A["c0"], 0, CH[0]); conv("u0", A["u0a"], A["u0"])
         conv("head", A["u0"], b["out"])
         return b["out"]
 
@@ -288,7 +298,7 @@ class UNet:
         """Velocity field [3][n^3] float64 on the device for one geometry:
         (g/nu) * kc_scale(porosity) * u_scale * network output on fluid
         voxels, 0 on solids."""
-        out = self.forward(mask_u8, 1, n)
+        out = self.forward(mask_u8, 1, n, fuse_concat=True)
         if out_u is None:
             out_u = self.torch.empty(3 * n ** 3, dtype=self.torch.float64, device=self.device)
         nn.velocity_out(out, mask_u8, g_over_nu * kc_scale(porosity) * self.u_scale, out_u)

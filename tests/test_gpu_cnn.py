@@ -113,6 +113,50 @@ def test_conv_dgrad_wgrad(NN, case):
     assert torch.equal(dw, dw2)
 
 
+@pytest.mark.parametrize("B,n,c1,c2,co", [(1, 32, 32, 16, 16), (1, 32, 64, 32, 32), (1, 16, 64, 64, 64),
+                                          (2, 16, 16, 16, 16), (1, 32, 16, 32, 32)])
+def test_conv_fwd_upcat_equals_concat_then_conv(NN, B, n, c1, c2, co):
+    """The fused decoder input (coarse tensor up-sampled and the skip tensor
+    read directly) gives the bits of nn_up_concat followed by the forward,
+    for bf16 and float32 outputs; c1 = 16 puts both sources in one
+    32-channel chunk."""
+    dev = torch.device("cuda")
+    coarse = _bf((B, n // 2, n // 2, n // 2, c1), 11).to(dev)
+    skip = _bf((B, n, n, n, c2), 12).to(dev)
+    ci = c1 + c2
+    w = _bf((27, co, ci), 13, (2.0 / (27 * ci)) ** 0.5).to(dev)
+    b = (torch.randn(co, generator=torch.Generator().manual_seed(14)) * 0.1).to(dev)
+    cat = torch.empty(B * n ** 3 * ci, dtype=torch.bfloat16, device=dev)
+    NN.up_concat(coarse, skip, cat, B, n, n, n, c1, c2)
+    for out_f32 in (True, False):
+        dt = torch.float32 if out_f32 else torch.bfloat16
+        d = NN.desc(B, n, n, n, ci, co, act=True, slope=0.1, out_f32=out_f32)
+        want = torch.empty(B * n ** 3 * co, dtype=dt, device=dev)
+        got = torch.empty_like(want)
+        NN.conv_fwd(d, cat, w, b, want)
+        NN.conv_fwd_upcat(d, coarse, c1, skip, w, b, got)
+        assert torch.equal(got, want), out_f32
+    # grids the staged kernel does not tile, and stride 2, are refused
+    with pytest.raises(Exception):
+        NN.conv_fwd_upcat(NN.desc(1, 8, 8, 8, ci, co), coarse, c1, skip, w, b, got)
+    with pytest.raises(Exception):
+        NN.conv_fwd_upcat(NN.desc(1, n, n, n, ci, co, stride=2), coarse, c1, skip, w, b, got)
+
+
+def test_unet_fused_concat_same_output(NN):
+    """The network's inference path (decoder inputs not concatenated) gives
+    the same output bits as the training path."""
+    from paper_1711_11468_amd.surrogate import UNet
+    dev = torch.device("cuda")
+    B, n = 2, 32
+    net = UNet(device=dev, seed=6)
+    g = torch.Generator().manual_seed(7)
+    mask = (torch.rand(B * n ** 3, generator=g) < 0.3).to(torch.uint8).to(dev)
+    a = net.forward(mask, B, n).clone()
+    f = net.forward(mask, B, n, fuse_concat=True).clone()
+    assert torch.equal(a, f)
+
+
 def test_unet_forward_backward_vs_reference(NN):
     """Whole network on a 16^3 periodic box, batch 2: output, loss and the
     parameter gradients against the float64 reference with the same
