@@ -402,6 +402,123 @@ k_conv_fwd_lds(const uint16_t* __restrict__ x, const uint16_t* __restrict__ xc, 
   }
 }
 
+// Stride-2 3x3x3 forward through LDS (the down-sampling layers), on output
+// grids whose W is a multiple of 16 and H and D even.  A workgroup computes
+// 16 x 2 x 4 (x, y, z) output voxels: it stages the 33 x 5 x 9 input voxels
+// they read (periodic halo included), 16 channels at a time, and each
+// wavefront takes one output z plane and two rows.  For a row of 16 outputs
+// the x taps read input voxels 2j, 2j + 1 and 2j + 2: the first two are
+// read from LDS, the third is the first moved one lane up, its last voxel a
+// broadcast.  K pairs two (z, y) taps of 16 channels per instruction, as in
+// the stride-1 16-channel chunk.
+constexpr int kS2TX = 16, kS2TY = 2, kS2TZ = 4;
+constexpr int kS2HX = 2 * kS2TX + 1, kS2HY = 2 * kS2TY + 1, kS2HZ = 2 * kS2TZ + 1;
+constexpr int kS2Halo = kS2HX * kS2HY * kS2HZ;  // 1485 voxels
+constexpr int kS2VS = 16 + kLdsPad;             // staged voxel stride (16 channels)
+
+template <int NB, bool OUTF32>
+__global__ void __launch_bounds__(256)
+k_conv_fwd_lds_s2(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
+                  const float* __restrict__ bias, void* __restrict__ y, int64_t n_tiles, int parts,
+                  Geom g) {
+  extern __shared__ __align__(16) uint16_t stage[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, kq = lane >> 4, half = kq >> 1;
+  int64_t t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= n_tiles * parts) return;
+  const int co0 = (int)(t % parts) * NB * 16;
+  t /= parts;
+  const int tx = g.Wo / kS2TX, ty = g.Ho / kS2TY, tz = g.Do / kS2TZ;
+  const int x0 = (int)(t % tx) * kS2TX;
+  t /= tx;
+  const int y0 = (int)(t % ty) * kS2TY;
+  t /= ty;
+  const int z0 = (int)(t % tz) * kS2TZ;
+  const int b = (int)(t / tz);
+  f4 acc[kS2TY][NB];
+#pragma unroll
+  for (int m = 0; m < kS2TY; ++m)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f4{0.f, 0.f, 0.f, 0.f};
+  const int64_t tap_stride = (int64_t)g.co * g.ci;
+  const int grp = 8 * (kq & 1);
+  const bf8 zero8 = {};
+  for (int c0 = 0; c0 < g.ci; c0 += 16) {
+    __syncthreads();  // the previous chunk has been read
+    for (int p = threadIdx.x; p < kS2Halo * 2; p += 256) {
+      const int v = p >> 1, piece = p & 1;
+      const int hx = v % kS2HX, hy = (v / kS2HX) % kS2HY, hz = v / (kS2HX * kS2HY);
+      const int gx = wrapi(2 * x0 + hx - 1, g.W), gy = wrapi(2 * y0 + hy - 1, g.H),
+                gz = wrapi(2 * z0 + hz - 1, g.D);
+      const int64_t gv = (((int64_t)b * g.D + gz) * g.H + gy) * g.W + gx;
+      *(uint4*)(stage + v * kS2VS + piece * 8) = *(const uint4*)(x + gv * g.ci + c0 + piece * 8);
+    }
+    __syncthreads();
+    const uint16_t* wbase = w + (int64_t)(co0 + row) * g.ci + c0 + grp;
+    // staged voxel (x = -1, y = -1) of the wave's output plane, lane's channels
+    const uint16_t* srow = stage + (2 * wave) * kS2HY * kS2HX * kS2VS + grp;
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+      const bool pad = 2 * p + 1 > 8;
+      const int ca = 2 * p, cb = pad ? ca : 2 * p + 1;
+      const int c = half ? cb : ca;  // (z, y) tap of this lane's half
+      const int dz = c / 3, dy = c % 3;
+      bf8 wf[3][NB];
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          wf[dx][nb] = *(const bf8*)(wbase + (int64_t)(3 * c + dx) * tap_stride + (int64_t)nb * 16 * g.ci);
+          if (pad && half) wf[dx][nb] = zero8;
+        }
+#pragma unroll
+      for (int m = 0; m < kS2TY; ++m) {
+        const uint16_t* rp = srow + (dz * kS2HY + 2 * m + dy) * kS2HX * kS2VS;
+        const bf8 ev = *(const bf8*)(rp + (2 * row) * kS2VS);          // input 2j - 1 (tap x - 1)
+        const bf8 od = *(const bf8*)(rp + (2 * row + 1) * kS2VS);      // input 2j (tap x)
+        const bf8 hi = *(const bf8*)(rp + (kS2HX - 1) * kS2VS);        // staged x = 32, broadcast
+        const bf8 nx = row_shift8(hi, ev, true);                        // input 2j + 1 (tap x + 1)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[0][nb], ev, acc[m][nb], 0, 0, 0);
+          acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[1][nb], od, acc[m][nb], 0, 0, 0);
+          acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[2][nb], nx, acc[m][nb], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < kS2TY; ++m) {
+    const int64_t vox = (((int64_t)b * g.Do + z0 + wave) * g.Ho + y0 + m) * g.Wo + x0 + row;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int cb = co0 + nb * 16 + 4 * kq;
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        v[e] = acc[m][nb][e] + (bias ? bias[cb + e] : 0.f);
+        if (g.act) v[e] = v[e] > 0.f ? v[e] : v[e] * g.slope;
+      }
+      if ((g.cstore & 3) == 0 && cb + 4 <= g.cstore) {
+        if (OUTF32) {
+          *(f4*)((float*)y + vox * g.cstore + cb) = f4{v[0], v[1], v[2], v[3]};
+        } else {
+          const uint2 pk = {(uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
+                            (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16)};
+          *(uint2*)((uint16_t*)y + vox * g.cstore + cb) = pk;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (cb + e >= g.cstore) continue;
+          if (OUTF32) ((float*)y)[vox * g.cstore + cb + e] = v[e];
+          else ((uint16_t*)y)[vox * g.cstore + cb + e] = f2bf(v[e]);
+        }
+      }
+    }
+  }
+}
+
 // ---- data gradient --------------------------------------------------------
 // dx[q] = sum over taps and output voxels p with s*p + off = q of W^T dy[p];
 // MT input-voxel tiles per wavefront as in the forward kernel.  For tap
@@ -1150,6 +1267,26 @@ static bool launch_fwd_lds(int nb, const uint16_t* x, const uint16_t* xc, int c1
   return true;
 }
 
+// The LDS stride-2 forward; false if the layer's output grid does not tile.
+template <bool F32>
+static bool launch_fwd_lds_s2(int nb, const uint16_t* x, const uint16_t* w, const float* bias, void* y,
+                              const Geom& g, hipStream_t s) {
+  if (g.Wo % kS2TX || g.Ho % kS2TY || g.Do % kS2TZ) return false;
+  const int64_t n_tiles = (int64_t)g.B * (g.Do / kS2TZ) * (g.Ho / kS2TY) * (g.Wo / kS2TX);
+  int per = 1;
+  for (int c = 4; c > 1; c /= 2)
+    if (nb % c == 0 && n_tiles * (nb / c) >= kLdsMinGroups) { per = c; break; }
+  const int parts = nb / per;
+  const dim3 grid(pad_xcd((unsigned)(n_tiles * parts))), block(256);
+  const size_t lds = (size_t)kS2Halo * kS2VS * 2;
+  switch (per) {
+    case 1: hipLaunchKernelGGL((k_conv_fwd_lds_s2<1, F32>), grid, block, lds, s, x, w, bias, y, n_tiles, parts, g); break;
+    case 2: hipLaunchKernelGGL((k_conv_fwd_lds_s2<2, F32>), grid, block, lds, s, x, w, bias, y, n_tiles, parts, g); break;
+    default: hipLaunchKernelGGL((k_conv_fwd_lds_s2<4, F32>), grid, block, lds, s, x, w, bias, y, n_tiles, parts, g); break;
+  }
+  return true;
+}
+
 template <int STRIDE, int TAPS, int MT>
 static void launch_dgrad_mt(int nb, const uint16_t* dy, const uint16_t* wt, float* dx, int acc,
                             const Geom& g, hipStream_t s) {
@@ -1218,6 +1355,12 @@ int nn_conv3d_fwd(const nn_conv_desc* d, const uint16_t* x, const uint16_t* w, c
   if (d->taps == 27 && d->stride == 1 &&
       (d->out_f32 ? launch_fwd_lds<true>(nb, x, nullptr, 0, w, bias, y, g, s)
                   : launch_fwd_lds<false>(nb, x, nullptr, 0, w, bias, y, g, s))) {
+    NN_HIP_CHECK("conv fwd");
+    return 0;
+  }
+  if (d->taps == 27 && d->stride == 2 &&
+      (d->out_f32 ? launch_fwd_lds_s2<true>(nb, x, w, bias, y, g, s)
+                  : launch_fwd_lds_s2<false>(nb, x, w, bias, y, g, s))) {
     NN_HIP_CHECK("conv fwd");
     return 0;
   }

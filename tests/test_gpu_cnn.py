@@ -36,13 +36,16 @@ CASES = [  # (batch, n, c_in, c_out, stride, taps)
 ]
 
 
-# grids the LDS forward tiles (W % 16, H % 4, D % 4): 32-channel chunks, a
+# grids the LDS forwards tile (stride 1: W % 16, H % 4, D % 4): 32-channel chunks, a
 # 32 + 16 split, three and four chunks, one, two and four 16-channel output
 # blocks per workgroup, and output channels split over workgroups on small
 # grids (16^3 with 64 outputs: four workgroups per block)
 FWD_CASES = CASES + [
     (1, 32, 32, 64, 1, 27), (1, 32, 48, 16, 1, 27), (1, 32, 96, 32, 1, 27),
     (1, 32, 128, 64, 1, 27), (2, 32, 64, 32, 1, 27), (1, 16, 64, 64, 1, 27),
+    # stride 2 through LDS (output W % 16, H % 2, D % 4): one, two and four
+    # output blocks, several 16-channel chunks, two tiles per output row
+    (1, 32, 16, 32, 2, 27), (1, 32, 32, 64, 2, 27), (2, 32, 64, 64, 2, 27), (1, 64, 16, 32, 2, 27),
 ]
 
 
