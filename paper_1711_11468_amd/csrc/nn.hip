@@ -744,14 +744,16 @@ k_conv_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dyp,
       }
     }
   }
-  if (do_bias) bias_partial[ck * g.co + tid] = bsum;
+  // one row of partials per chunk: the weights, then the bias
+  const int64_t row_len = (int64_t)TAPS * g.co * g.ci + g.co;
+  if (do_bias) bias_partial[ck * row_len + tid] = bsum;
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     const int tile = wave + 4 * j;
     if (tile < ntiles) {
       const int tl = tile / nt, t2 = tile - tl * nt;
       const int mo = t2 / nbi, ni = t2 - mo * nbi;
-      float* out = partial + (ck * TAPS + tap0 + tl) * g.co * g.ci;
+      float* out = partial + ck * row_len + (int64_t)(tap0 + tl) * g.co * g.ci;
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         out[(mo * 16 + 4 * kq + r) * g.ci + ni * 16 + row] = acc[j][r];
@@ -763,25 +765,30 @@ k_conv_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dyp,
 // consecutive chunks (grid y = segment), then the segment sums in order.
 constexpr int kSegLen = 16;
 
+// Fixed-order sum of the per-chunk partial rows (row stride `stride`, the
+// first n columns) over segments of kSegLen chunks.
 __global__ void k_sum_segments(const float* __restrict__ partial, float* __restrict__ seg,
-                               int64_t n, int64_t chunks) {
+                               int64_t n, int64_t stride, int64_t chunks) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t c0 = (int64_t)blockIdx.y * kSegLen;
   int64_t c1 = c0 + kSegLen;
   if (c1 > chunks) c1 = chunks;
   float s = 0.f;
-  for (int64_t c = c0; c < c1; ++c) s += partial[c * n + i];
+  for (int64_t c = c0; c < c1; ++c) s += partial[c * stride + i];
   seg[(int64_t)blockIdx.y * n + i] = s;
 }
 
-__global__ void k_sum_chunks(const float* __restrict__ partial, float* __restrict__ out,
-                             int64_t n, int64_t chunks) {
+// Sum of the segment rows in order; columns below na go to out_a, the rest
+// to out_b (the weight and bias gradients of one call).
+__global__ void k_sum_chunks(const float* __restrict__ seg, float* __restrict__ out_a, int64_t na,
+                             float* __restrict__ out_b, int64_t n, int64_t segs) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float s = 0.f;
-  for (int64_t c = 0; c < chunks; ++c) s += partial[c * n + i];
-  out[i] = s;
+  for (int64_t c = 0; c < segs; ++c) s += seg[c * n + i];
+  if (i < na) out_a[i] = s;
+  else out_b[i - na] = s;
 }
 
 // ---- elementwise ----------------------------------------------------------
@@ -1439,26 +1446,22 @@ int nn_conv3d_wgrad(const nn_conv_desc* d, const uint16_t* x, const uint16_t* dy
   const int64_t chunk = wgrad_chunk(d, g, &chunks);
   const int64_t nw = (int64_t)d->taps * d->c_out * d->c_in;
   const int64_t segs = (chunks + kSegLen - 1) / kSegLen;
-  // workspace: [chunks][nw] partials, [segs][nw] segment sums, then the
-  // same two areas for the bias (co each)
-  float* wseg = workspace + chunks * nw;
-  float* bpart = wseg + segs * nw;
-  float* bseg = bpart + chunks * d->c_out;
+  // workspace: [chunks][nw + c_out] partial rows (weights, then bias), then
+  // [segs][n] segment sums of the n columns wanted; one pair of summing
+  // launches covers both gradients
+  const int64_t row = nw + d->c_out;
+  const int64_t n = db ? row : nw;
+  float* seg = workspace + chunks * row;
   int tpb, tpw;
   size_t lds;
   wgrad_plan(d, &tpb, &tpw, &lds);
-  float* bp = db ? bpart : nullptr;
+  float* bp = db ? workspace + nw : nullptr;
   if (d->taps == 1) launch_wgrad_tpw<1, 1>(tpw, tpb, lds, x, dy, workspace, bp, chunk, chunks, g, s);
   else if (d->stride == 1) launch_wgrad_tpw<1, 27>(tpw, tpb, lds, x, dy, workspace, bp, chunk, chunks, g, s);
   else launch_wgrad_tpw<2, 27>(tpw, tpb, lds, x, dy, workspace, bp, chunk, chunks, g, s);
-  hipLaunchKernelGGL(k_sum_segments, dim3(nblk(nw, 256), (unsigned)segs), dim3(256), 0, s, workspace,
-                     wseg, nw, chunks);
-  hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(nw, 256)), dim3(256), 0, s, wseg, dw, nw, segs);
-  if (db) {
-    hipLaunchKernelGGL(k_sum_segments, dim3(1, (unsigned)segs), dim3(256), 0, s, bpart, bseg,
-                       (int64_t)d->c_out, chunks);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, s, bseg, db, (int64_t)d->c_out, segs);
-  }
+  hipLaunchKernelGGL(k_sum_segments, dim3(nblk(n, 256), (unsigned)segs), dim3(256), 0, s, workspace,
+                     seg, n, row, chunks);
+  hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(n, 256)), dim3(256), 0, s, seg, dw, nw, db, n, segs);
   NN_HIP_CHECK("conv wgrad");
   return 0;
 }
