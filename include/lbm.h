@@ -295,6 +295,9 @@ int lbm_step_diag(lbm_ctx* ctx, lbm_stats* out);
  *   node outside the outermost fluid layer); u_y = u_z = 0.
  * LBM_VERIFY_DUCT: the Fourier series of steady flow in a rectangular duct
  *   with half-widths a = (ny-2)/2, b = (nz-2)/2, walls placed likewise.
+ *   Both forms assume the walls are solid boundary layers of the mask; a
+ *   box whose walls are the faces of non-periodic axes compares with
+ *   LBM_VERIFY_REFERENCE.
  * LBM_VERIFY_REFERENCE: ref_dev is a device [3][N] double field.
  * Synchronises.  Errors: EINVAL, EDEVICE. */
 int lbm_verify(lbm_ctx* ctx, int32_t kind, const double* ref_dev,
