@@ -3,7 +3,7 @@
  * 3D convolutional network that maps a solid mask (and the driving force
  * direction) to the steady velocity field of the lattice Boltzmann solver.
  * The network is not part of the paper; it provides initial states for the
- * solver, which stays the judge of the steady state (it runs from the
+ * solver, which still decides when the steady state is reached (it runs from the
  * predicted equilibrium until its own residual criterion is met).
  *
  * Conventions:

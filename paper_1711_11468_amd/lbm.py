@@ -301,7 +301,7 @@ class Lattice:
         for ever.  Intervals 100, 52 and 120 (gcd 4) leave no other period
         hidden from all three, e.g. an acoustic mode of the box whose period
         divides 100; since a mode's swing over an interval also depends on
-        its phase, the intervals were chosen (by simulating the judge on
+        its phase, the intervals were chosen (by simulating the criterion on
         decaying sinusoids of every period from 10 to 300 updates and every
         phase) so that no such mode passes with an amplitude above ~15 tol.
         A failed confirmation continues the run (the next check spans

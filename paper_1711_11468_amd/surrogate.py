@@ -2,7 +2,7 @@
 steady velocity field of the body-force-driven flow, trained on the GPU by
 the library's own BF16 MFMA kernels (forward, data gradient, weight
 gradient, Adam), and used to start the solver from equilibrium at the
-predicted velocity.  The solver remains the judge: it iterates from the
+predicted velocity.  The solver still decides convergence: it iterates from the
 prediction until its own residual criterion is met.
 
 Network (channels-last, circular padding everywhere since the porous boxes

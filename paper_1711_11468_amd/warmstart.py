@@ -140,7 +140,7 @@ def cycle_mean_velocity(lat, k=4):
 def compare(net, seed, n):
     """Cold (rest) versus warm (network prediction) start on one geometry.
     The warm time includes the inference; both runs stop by the same
-    judge.  Errors are relative L2 velocity norms against the cold-start
+    convergence test.  Errors are relative L2 velocity norms against the cold-start
     steady field: the prediction's (the library's verify kernel on a
     lattice initialised with it, before any update) and the warm run's
     converged field's (4-update means of both, see cycle_mean_velocity)."""

@@ -1,5 +1,5 @@
 """Why the learned warm start does not pay: updates to the steady-state
-judge's target from starts of controlled error structure, on held-out
+convergence target from starts of controlled error structure, on held-out
 porous boxes (FP64 list form, half-way bounce-back, the warm-start physics).
 
 Starts: rest (cold); the exact steady velocity (from a run converged to a

@@ -295,7 +295,7 @@ def test_ria_validation():
     assert s.bytes_per_update - 304 == pytest.approx((s1.bytes_per_update - 304) / 2)
 
 
-def test_steady_judge_sees_oscillations_that_divide_the_check_interval():
+def test_steady_criterion_sees_oscillations_that_divide_the_check_interval():
     """run_to_steady confirms a passing 100-update residual over further
     intervals of 52 and 120 updates: a field oscillating with period 50 (invisible
     to the 100-update residual) keeps running until its amplitude has

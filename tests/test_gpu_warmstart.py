@@ -1,7 +1,7 @@
 """The learned warm start end to end on held-out porous boxes, with the
 network trained by the library's own kernels (weights committed with the
 package): the prediction is accurate to the stated level, both starts
-converge to the same field (the solver stays the judge), and the warm start
+converge to the same field (the solver still decides convergence), and the warm start
 reaches the residual target in fewer updates and less wall time, inference
 included.  A warm start from the exact steady field shows the gain an
 accurate prediction buys."""
@@ -38,7 +38,7 @@ def held_out(WS):
 
 
 def test_held_out_both_starts_converge_to_one_field(held_out):
-    """Both runs meet the judge, and their converged fields, averaged over
+    """Both runs meet the convergence test, and their converged fields, averaged over
     4 updates so that the corner limit cycle cancels, agree far below the
     residual target: the warm start settles on the same steady state (the
     instantaneous fields differ by the cycle, ~1e-3, whose amplitude

@@ -306,7 +306,7 @@ def test_oracle_corner_limit_cycle(bounce, period):
     bounce-back at staircase corners leaves a component of period 2
     (half-way) or 4 (full-way; whether it appears depends on the corners
     present: this box has them) that does not decay, while the residual
-    over a whole period is at round-off.  The steady-state judge relies on
+    over a whole period is at round-off.  The steady-state criterion relies on
     this (its check intervals are multiples of 4)."""
     mask, _, _ = I.spheres_mask(24, 24, 24, 0, 0.55, 3.0, 5.0)
     g = (1e-6, 0.0, 0.0)
