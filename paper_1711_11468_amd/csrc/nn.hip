@@ -519,6 +519,38 @@ k_conv_fwd_lds_s2(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w
   }
 }
 
+// 1x1x1 layer with at most four stored float32 outputs (the network's
+// head): one thread per voxel holds its CI inputs and forms the stored
+// outputs' dot products in float32; the weights and bias are the same for
+// every thread.
+template <int CI>
+__global__ void k_conv1x1_few(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
+                              const float* __restrict__ bias, float* __restrict__ y, int64_t m,
+                              int cstore, int act, float slope) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= m) return;
+  float xv[CI];
+#pragma unroll
+  for (int q = 0; q < CI / 8; ++q) {
+    const uint4 u = *(const uint4*)(x + v * CI + 8 * q);
+    const uint32_t p[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      xv[8 * q + 2 * h] = bf2f((uint16_t)(p[h] & 0xffffu));
+      xv[8 * q + 2 * h + 1] = bf2f((uint16_t)(p[h] >> 16));
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c >= cstore) break;
+    float sum = bias ? bias[c] : 0.f;
+#pragma unroll
+    for (int k = 0; k < CI; ++k) sum += bf2f(w[c * CI + k]) * xv[k];
+    if (act) sum = sum > 0.f ? sum : sum * slope;
+    y[v * cstore + c] = sum;
+  }
+}
+
 // ---- data gradient --------------------------------------------------------
 // dx[q] = sum over taps and output voxels p with s*p + off = q of W^T dy[p];
 // MT input-voxel tiles per wavefront as in the forward kernel.  For tap
@@ -1369,6 +1401,18 @@ int nn_conv3d_fwd(const nn_conv_desc* d, const uint16_t* x, const uint16_t* w, c
       (d->out_f32 ? launch_fwd_lds_s2<true>(nb, x, w, bias, y, g, s)
                   : launch_fwd_lds_s2<false>(nb, x, w, bias, y, g, s))) {
     NN_HIP_CHECK("conv fwd");
+    return 0;
+  }
+  if (d->taps == 1 && d->stride == 1 && d->out_f32 && d->c_store <= 4 &&
+      (d->c_in == 16 || d->c_in == 32) && ((uintptr_t)x & 15) == 0) {
+    const dim3 grid(nblk(g.m_out, 256)), block(256);
+    if (d->c_in == 16)
+      hipLaunchKernelGGL(k_conv1x1_few<16>, grid, block, 0, s, x, w, bias, (float*)y, g.m_out, d->c_store,
+                         d->act, d->slope);
+    else
+      hipLaunchKernelGGL(k_conv1x1_few<32>, grid, block, 0, s, x, w, bias, (float*)y, g.m_out, d->c_store,
+                         d->act, d->slope);
+    NN_HIP_CHECK("conv fwd 1x1");
     return 0;
   }
   if (d->taps == 1) {

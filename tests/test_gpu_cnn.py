@@ -85,6 +85,22 @@ def test_conv_forward_stored_channels(NN, n, ci, co, c_store):
         assert rel(got, ref) <= (2e-6 if out_f32 else 8e-3), (out_f32, rel(got, ref))
 
 
+@pytest.mark.parametrize("ci,c_store,act", [(16, 3, False), (16, 4, True), (32, 3, True), (32, 1, False)])
+def test_conv_1x1_few_outputs(NN, ci, c_store, act):
+    """The 1x1x1 head form (float32 output, at most four stored channels)
+    against the float64 reference."""
+    B, n, co = 2, 8, 16
+    x = _bf((B, n, n, n, ci), 15)
+    w = _bf((1, co, ci), 16, (2.0 / ci) ** 0.5)
+    b = torch.randn(co, generator=torch.Generator().manual_seed(17)) * 0.1
+    dev = torch.device("cuda")
+    y = torch.empty(B * n ** 3 * c_store, dtype=torch.float32, device=dev)
+    d = NN.desc(B, n, n, n, ci, co, c_store=c_store, taps=1, act=act, slope=0.1, out_f32=True)
+    NN.conv_fwd(d, x.to(dev), w.to(dev), b.to(dev), y)
+    ref = R.conv(x.double(), w.double(), b.double(), stride=1, taps=1, act=act)[..., :c_store]
+    assert rel(y.cpu().double().reshape(ref.shape), ref) <= 2e-6
+
+
 @pytest.mark.parametrize("case", CASES)
 def test_conv_dgrad_wgrad(NN, case):
     B, n, ci, co, s, taps = case
