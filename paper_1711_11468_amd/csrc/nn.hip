@@ -312,7 +312,7 @@ __device__ __forceinline__ void conv_lds_chunk(const uint16_t* __restrict__ srow
   }
 }
 
-template <int NB, bool OUTF32>
+template <int NB, bool OUTF32, bool ACC = false>
 __global__ void __launch_bounds__(256)
 k_conv_fwd_lds(const uint16_t* __restrict__ x, const uint16_t* __restrict__ xc, int c1,
                const uint16_t* __restrict__ w, const float* __restrict__ bias, void* __restrict__ y,
@@ -384,7 +384,13 @@ k_conv_fwd_lds(const uint16_t* __restrict__ x, const uint16_t* __restrict__ xc, 
       }
       if ((g.cstore & 3) == 0 && cb + 4 <= g.cstore) {  // aligned four-channel store
         if (OUTF32) {
-          *(f4*)((float*)y + vox * g.cstore + cb) = f4{v[0], v[1], v[2], v[3]};
+          f4* o = (f4*)((float*)y + vox * g.cstore + cb);
+          if (ACC) {
+            const f4 old = *o;
+            *o = f4{old[0] + v[0], old[1] + v[1], old[2] + v[2], old[3] + v[3]};
+          } else {
+            *o = f4{v[0], v[1], v[2], v[3]};
+          }
         } else {
           const uint2 pk = {(uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
                             (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16)};
@@ -394,8 +400,12 @@ k_conv_fwd_lds(const uint16_t* __restrict__ x, const uint16_t* __restrict__ xc, 
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           if (cb + e >= g.cstore) continue;
-          if (OUTF32) ((float*)y)[vox * g.cstore + cb + e] = v[e];
-          else ((uint16_t*)y)[vox * g.cstore + cb + e] = f2bf(v[e]);
+          if (OUTF32) {
+            float* o = (float*)y + vox * g.cstore + cb + e;
+            *o = ACC ? *o + v[e] : v[e];
+          } else {
+            ((uint16_t*)y)[vox * g.cstore + cb + e] = f2bf(v[e]);
+          }
         }
       }
     }
@@ -639,15 +649,20 @@ k_conv_dgrad(const uint16_t* __restrict__ dyp, const uint16_t* __restrict__ wt,
   }
 }
 
+// wt[tap'][ci][co] = w[tap][co][ci], with tap' = tap, or with the tap
+// mirrored through the centre (tap' = taps - 1 - tap, the offset negated
+// on every axis) when flip is set: the data gradient of a stride-1 layer is
+// then the forward convolution of dy with wt.
 __global__ void k_transpose_w(const uint16_t* __restrict__ w, uint16_t* __restrict__ wt, int taps,
-                              int co, int ci) {
+                              int co, int ci, int flip) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)taps * co * ci;
   if (e >= n) return;
   const int c_in = (int)(e % ci);
   const int c_out = (int)((e / ci) % co);
   const int tap = (int)(e / ((int64_t)ci * co));
-  wt[((int64_t)tap * ci + c_in) * co + c_out] = w[e];
+  const int tw = flip ? taps - 1 - tap : tap;
+  wt[((int64_t)tw * ci + c_in) * co + c_out] = w[e];
 }
 
 // ---- weight gradient ------------------------------------------------------
@@ -1283,7 +1298,7 @@ static void launch_fwd_nb(int nb, const uint16_t* x, const uint16_t* w, const fl
 
 // The LDS forward for stride-1 3x3x3 layers on grids it tiles; false if
 // the layer does not qualify (then the per-wavefront kernel runs).
-template <bool F32>
+template <bool F32, bool ACC = false>
 static bool launch_fwd_lds(int nb, const uint16_t* x, const uint16_t* xc, int c1, const uint16_t* w,
                            const float* bias, void* y, const Geom& g, hipStream_t s) {
   if (g.W % kLdsTX || g.H % kLdsTY || g.D % kLdsTZ) return false;
@@ -1299,9 +1314,9 @@ static bool launch_fwd_lds(int nb, const uint16_t* x, const uint16_t* xc, int c1
   // elements per voxel, which lets more workgroups share a compute unit)
   const size_t lds = (size_t)kLdsHalo * ((g.ci < kLdsChunk ? g.ci : kLdsChunk) + kLdsPad) * 2;
   switch (per) {
-    case 1: hipLaunchKernelGGL((k_conv_fwd_lds<1, F32>), grid, block, lds, s, x, xc, c1, w, bias, y, n_tiles, parts, g); break;
-    case 2: hipLaunchKernelGGL((k_conv_fwd_lds<2, F32>), grid, block, lds, s, x, xc, c1, w, bias, y, n_tiles, parts, g); break;
-    default: hipLaunchKernelGGL((k_conv_fwd_lds<4, F32>), grid, block, lds, s, x, xc, c1, w, bias, y, n_tiles, parts, g); break;
+    case 1: hipLaunchKernelGGL((k_conv_fwd_lds<1, F32, ACC>), grid, block, lds, s, x, xc, c1, w, bias, y, n_tiles, parts, g); break;
+    case 2: hipLaunchKernelGGL((k_conv_fwd_lds<2, F32, ACC>), grid, block, lds, s, x, xc, c1, w, bias, y, n_tiles, parts, g); break;
+    default: hipLaunchKernelGGL((k_conv_fwd_lds<4, F32, ACC>), grid, block, lds, s, x, xc, c1, w, bias, y, n_tiles, parts, g); break;
   }
   return true;
 }
@@ -1460,8 +1475,24 @@ int nn_conv3d_dgrad(const nn_conv_desc* d, const uint16_t* dy, const uint16_t* w
   const Geom g = make_geom(d);
   hipStream_t s = (hipStream_t)stream;
   const int64_t nw = (int64_t)d->taps * d->c_out * d->c_in;
+  // stride-1 3x3x3 layers on grids the LDS forward tiles: dx is the forward
+  // convolution of dy (c_out channels in, c_in out, no bias or activation)
+  // with the mirrored, transposed weights, added to dx when accumulating
+  const bool lds = d->taps == 27 && d->stride == 1 && g.W % kLdsTX == 0 && g.H % kLdsTY == 0 &&
+                   g.D % kLdsTZ == 0 && ((uintptr_t)dy & 15) == 0 && ((uintptr_t)w_t & 15) == 0;
   hipLaunchKernelGGL(k_transpose_w, dim3(nblk(nw, 256)), dim3(256), 0, s, w, w_t, d->taps, d->c_out,
-                     d->c_in);
+                     d->c_in, lds ? 1 : 0);
+  if (lds) {
+    Geom gt = g;
+    gt.ci = g.co;
+    gt.co = g.ci;
+    gt.cstore = g.ci;
+    gt.act = 0;
+    if (accumulate) launch_fwd_lds<true, true>(d->c_in / 16, dy, nullptr, 0, w_t, nullptr, dx, gt, s);
+    else launch_fwd_lds<true, false>(d->c_in / 16, dy, nullptr, 0, w_t, nullptr, dx, gt, s);
+    NN_HIP_CHECK("conv dgrad");
+    return 0;
+  }
   const int nb = d->c_in / 16;
   if (d->taps == 1) launch_dgrad_nb<1, 1>(nb, dy, w_t, dx, accumulate, g, s);
   else if (d->stride == 1) launch_dgrad_nb<1, 27>(nb, dy, w_t, dx, accumulate, g, s);

@@ -116,7 +116,9 @@ def train(net, masks, labels, n, epochs, batch=4, lr=3e-4, seed=0, log=None, war
             t = labels.index_select(0, idx).reshape(-1)
             loss = net.train_step(m, t, batch, n, lr=step_lr)
             losses.append(loss.clone())
-        mean = float(torch.stack(losses).mean().item()) if losses else float("nan")
+        # the per-step losses come back to the host once per epoch and are
+        # averaged there
+        mean = float(np.mean(torch.cat(losses).cpu().numpy())) if losses else float("nan")
         history.append(mean)
         if log:
             log("epoch %d: loss %.5f (lr now %.1e)" % (ep, mean, step_lr))

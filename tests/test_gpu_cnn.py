@@ -124,6 +124,9 @@ def test_conv_dgrad_wgrad(NN, case):
     (out * dy.double()).sum().backward()
     got_dx = dx.cpu().double().reshape(xr.shape) - 0.5
     assert rel(got_dx, xr.grad) <= 2e-6
+    # overwriting form: the 0.5 already in dx is replaced
+    NN.conv_dgrad(d, dy.to(dev), w.to(dev), wt, dx, accumulate=False)
+    assert rel(dx.cpu().double().reshape(xr.shape), xr.grad) <= 2e-6
     assert rel(dw.cpu().double().reshape(wr.shape), wr.grad) <= 2e-5
     assert rel(db.cpu().double(), br.grad) <= 2e-5
     # deterministic: a second run gives identical bits
