@@ -808,6 +808,160 @@ k_conv_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dyp,
   }
 }
 
+// Weight gradient of stride-1 3x3x3 layers with 16 or 32 output channels on
+// grids of 16 x 4 x 4 bricks (the LDS forward's tiles).  A workgroup owns a
+// range of bricks and one 16-channel input block (grid y); per brick it
+// stages the brick's dy, transposed to [channel][voxel], and its 18 x 6 x 6 input halo,
+// transposed to [channel][halo row][x] (rows of 24 elements), once for all
+// 27 taps.  Each of the nine wavefronts owns one (dz, dy) tap pair and its
+// three x taps.  The K dimension of v_mfma_f32_16x16x32_bf16 is 32 voxels
+// of two brick rows and a lane's eight voxels are consecutive in x, so the
+// input operands of the three x taps come from one 16-byte and one 4-byte
+// LDS read, taken at offsets of 0, 1 and 2 elements.  The bias gradient is
+// the product of dy with an all-ones operand, one K block per wavefront.
+constexpr int kWbRowX = 24;                          // staged halo row (18 used)
+constexpr int kWbRows = kLdsHY * kLdsHZ;             // 36 halo rows
+constexpr int kWbChan = kWbRows * kWbRowX;           // elements per staged input channel
+constexpr int kWbBrick = kLdsTX * kLdsTY * kLdsTZ;   // 256 voxels
+constexpr int kWbThreads = 576;                      // nine wavefronts
+
+// Channel j of voxels a and c (eight channels each) as one 4-byte word in
+// row j of dst (rows `stride` elements apart).
+__device__ __forceinline__ void store_pairs(uint16_t* dst, int stride, const uint4& a, const uint4& c) {
+  const uint32_t u[4] = {a.x, a.y, a.z, a.w}, v[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int h = j >> 1, sh = (j & 1) * 16;
+    *(uint32_t*)(dst + j * stride) = ((u[h] >> sh) & 0xffffu) | (((v[h] >> sh) & 0xffffu) << 16);
+  }
+}
+
+__device__ __forceinline__ bf8 as_bf8(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  union U { bf8 f; uint32_t i[4]; } r;
+  r.i[0] = a; r.i[1] = b; r.i[2] = c; r.i[3] = d;
+  return r.f;
+}
+
+template <int NCO>
+__global__ void __launch_bounds__(kWbThreads)
+k_conv_wgrad_brick(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dyp,
+                   float* __restrict__ partial, int64_t chunks, int64_t per_chunk, int with_bias,
+                   Geom g) {
+  __shared__ __align__(16) uint16_t xs[16 * kWbChan];
+  __shared__ __align__(16) uint16_t dys[NCO * 16 * kWbBrick];
+  __shared__ float bsum[8][NCO * 16];
+  constexpr int co = NCO * 16;
+  // the wavefront index as a scalar: the bias product below is taken under
+  // a test of it, which must be a branch of the whole wavefront (matrix
+  // instructions do not honour the lane mask)
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t ck = xcd_tile(blockIdx.x, gridDim.x);
+  if (ck >= chunks) return;  // padding workgroup (before any barrier)
+  const int tx = g.W / kLdsTX, ty = g.H / kLdsTY, tz = g.D / kLdsTZ;
+  const int64_t n_bricks = (int64_t)g.B * tz * ty * tx;
+  const int64_t br0 = ck * per_chunk;
+  const int64_t br1 = br0 + per_chunk < n_bricks ? br0 + per_chunk : n_bricks;
+  const int row = lane & 15, grp = lane >> 4;
+  const int dzw = wave / 3, dyw = wave % 3;  // the wavefront's (dz, dy) tap pair, offsets + 1
+  const int xo = 8 * (grp & 1);              // first x of the lane's eight voxels
+  float* out = partial + ck * ((int64_t)27 * co * g.ci + co);
+  const bf8 ones = as_bf8(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u);
+  f4 bacc[NCO];
+#pragma unroll
+  for (int mo = 0; mo < NCO; ++mo) bacc[mo] = f4{0.f, 0.f, 0.f, 0.f};
+  const int cb = blockIdx.y;  // the input block
+  {
+    f4 acc[NCO][3];
+#pragma unroll
+    for (int mo = 0; mo < NCO; ++mo)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc[mo][k] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t br = br0; br < br1; ++br) {
+      int64_t t = br;
+      const int x0 = (int)(t % tx) * kLdsTX;
+      t /= tx;
+      const int y0 = (int)(t % ty) * kLdsTY;
+      t /= ty;
+      const int z0 = (int)(t % tz) * kLdsTZ;
+      const int b = (int)(t / tz);
+      __syncthreads();  // the previous brick's operands are consumed
+      // input halo: items of two x neighbours x eight channels
+      for (int it = tid; it < kWbRows * 18; it += kWbThreads) {
+        const int q = it % 9, h = (it / 9) & 1, r = it / 18;
+        const int hy = r % kLdsHY, hz = r / kLdsHY;
+        const int gz = wrapi(z0 + hz - 1, g.D), gy = wrapi(y0 + hy - 1, g.H);
+        const int64_t rb = (((int64_t)b * g.D + gz) * g.H + gy) * g.W;
+        const int gx0 = wrapi(x0 + 2 * q - 1, g.W), gx1 = wrapi(x0 + 2 * q, g.W);
+        const uint4 a = *(const uint4*)(x + (rb + gx0) * g.ci + cb * 16 + h * 8);
+        const uint4 c = *(const uint4*)(x + (rb + gx1) * g.ci + cb * 16 + h * 8);
+        store_pairs(xs + h * 8 * kWbChan + r * kWbRowX + 2 * q, kWbChan, a, c);
+      }
+      // dy of the brick: rows of 16 voxels, items of two voxels x eight channels
+      for (int it = tid; it < 16 * 8 * 2 * NCO; it += kWbThreads) {
+        const int q = it % 8, h = (it / 8) % (2 * NCO), r = it / (16 * NCO);
+        const int64_t vox = (((int64_t)b * g.D + z0 + r / kLdsTY) * g.H + y0 + r % kLdsTY) * g.W + x0 + 2 * q;
+        const uint4 a = *(const uint4*)(dyp + vox * co + h * 8);
+        const uint4 c = *(const uint4*)(dyp + (vox + 1) * co + h * 8);
+        store_pairs(dys + h * 8 * kWbBrick + r * 16 + 2 * q, kWbBrick, a, c);
+      }
+      __syncthreads();
+#pragma unroll 2
+      for (int kb = 0; kb < 8; ++kb) {
+        const int r = 2 * kb + (grp >> 1);  // brick row of the lane's voxels
+        bf8 av[NCO];
+#pragma unroll
+        for (int mo = 0; mo < NCO; ++mo) av[mo] = *(const bf8*)(dys + (mo * 16 + row) * kWbBrick + r * 16 + xo);
+        const int hr = (r / kLdsTY + dzw) * kLdsHY + r % kLdsTY + dyw;
+        const uint16_t* xp = xs + row * kWbChan + hr * kWbRowX + xo;
+        const uint4 lo = *(const uint4*)xp;
+        const uint32_t hi = *(const uint32_t*)(xp + 8);
+        const bf8 bm = as_bf8(lo.x, lo.y, lo.z, lo.w);  // dx = -1
+        const bf8 b0 = as_bf8((lo.x >> 16) | (lo.y << 16), (lo.y >> 16) | (lo.z << 16),
+                              (lo.z >> 16) | (lo.w << 16), (lo.w >> 16) | (hi << 16));  // dx = 0
+        const bf8 bp = as_bf8(lo.y, lo.z, lo.w, hi);    // dx = +1
+#pragma unroll
+        for (int mo = 0; mo < NCO; ++mo) {
+          acc[mo][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mo], bm, acc[mo][0], 0, 0, 0);
+          acc[mo][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mo], b0, acc[mo][1], 0, 0, 0);
+          acc[mo][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mo], bp, acc[mo][2], 0, 0, 0);
+        }
+        if (with_bias && cb == 0 && kb == wave) {
+#pragma unroll
+          for (int mo = 0; mo < NCO; ++mo)
+            bacc[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mo], ones, bacc[mo], 0, 0, 0);
+        }
+      }
+    }
+    // this input block's columns of the chunk's partial row
+#pragma unroll
+    for (int mo = 0; mo < NCO; ++mo)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int tap = dzw * 9 + dyw * 3 + k;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          out[((int64_t)tap * co + mo * 16 + 4 * grp + e) * g.ci + cb * 16 + row] = acc[mo][k][e];
+      }
+  }
+  if (with_bias && cb == 0) {
+    // every column of the all-ones product holds the sum; column 0, in a
+    // fixed order over the eight K blocks
+    if (wave < 8 && row == 0) {
+#pragma unroll
+      for (int mo = 0; mo < NCO; ++mo)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bsum[wave][mo * 16 + 4 * grp + e] = bacc[mo][e];
+    }
+    __syncthreads();
+    if (tid < co) {
+      float sum = 0.f;
+#pragma unroll
+      for (int w = 0; w < 8; ++w) sum += bsum[w][tid];
+      out[(int64_t)27 * co * g.ci + tid] = sum;
+    }
+  }
+}
+
 // Sum chunk partials in a fixed order, in two passes: segments of kSegLen
 // consecutive chunks (grid y = segment), then the segment sums in order.
 constexpr int kSegLen = 16;
@@ -1531,7 +1685,18 @@ int nn_conv3d_wgrad(const nn_conv_desc* d, const uint16_t* x, const uint16_t* dy
   size_t lds;
   wgrad_plan(d, &tpb, &tpw, &lds);
   float* bp = db ? workspace + nw : nullptr;
-  if (d->taps == 1) launch_wgrad_tpw<1, 1>(tpw, tpb, lds, x, dy, workspace, bp, chunk, chunks, g, s);
+  const bool brick = d->taps == 27 && d->stride == 1 && (d->c_out == 16 || d->c_out == 32) &&
+                     g.W % kLdsTX == 0 && g.H % kLdsTY == 0 && g.D % kLdsTZ == 0 &&
+                     ((uintptr_t)x & 15) == 0 && ((uintptr_t)dy & 15) == 0;
+  if (brick) {
+    const int64_t n_bricks = g.m_out / kWbBrick;
+    const int64_t per = (n_bricks + chunks - 1) / chunks;
+    const dim3 grid(pad_xcd((unsigned)chunks), d->c_in / 16), block(kWbThreads);
+    if (d->c_out == 16)
+      hipLaunchKernelGGL(k_conv_wgrad_brick<1>, grid, block, 0, s, x, dy, workspace, chunks, per, db ? 1 : 0, g);
+    else
+      hipLaunchKernelGGL(k_conv_wgrad_brick<2>, grid, block, 0, s, x, dy, workspace, chunks, per, db ? 1 : 0, g);
+  } else if (d->taps == 1) launch_wgrad_tpw<1, 1>(tpw, tpb, lds, x, dy, workspace, bp, chunk, chunks, g, s);
   else if (d->stride == 1) launch_wgrad_tpw<1, 27>(tpw, tpb, lds, x, dy, workspace, bp, chunk, chunks, g, s);
   else launch_wgrad_tpw<2, 27>(tpw, tpb, lds, x, dy, workspace, bp, chunk, chunks, g, s);
   hipLaunchKernelGGL(k_sum_segments, dim3(nblk(n, 256), (unsigned)segs), dim3(256), 0, s, workspace,
