@@ -101,6 +101,23 @@ def test_conv_1x1_few_outputs(NN, ci, c_store, act):
     assert rel(y.cpu().double().reshape(ref.shape), ref) <= 2e-6
 
 
+@pytest.mark.parametrize("n", [4096 * 8, 1001, 8])
+def test_lrelu_bwd_bits(NN, n):
+    """Leaky-ReLU backward (eight elements per thread when n % 8 == 0, one
+    otherwise) against the same selection and round-to-nearest-even bf16
+    conversion on the CPU, bit for bit."""
+    g = torch.Generator().manual_seed(21)
+    dx = torch.randn(n, generator=g, dtype=torch.float32)
+    y = torch.randn(n, generator=g).to(torch.bfloat16)
+    y[::7] = 0.0
+    slope = 0.1
+    dev = torch.device("cuda")
+    out = torch.empty(n, dtype=torch.bfloat16, device=dev)
+    NN.lrelu_bwd(dx.to(dev), y.to(dev), out, slope)
+    ref = torch.where(y.float() > 0, dx, dx * slope).to(torch.bfloat16)
+    assert torch.equal(out.cpu().view(torch.int16), ref.view(torch.int16))
+
+
 @pytest.mark.parametrize("case", CASES)
 def test_conv_dgrad_wgrad(NN, case):
     B, n, ci, co, s, taps = case
