@@ -565,8 +565,13 @@ __global__ void k_conv1x1_few(const uint16_t* __restrict__ x, const uint16_t* __
 // dx[q] = sum over taps and output voxels p with s*p + off = q of W^T dy[p];
 // MT input-voxel tiles per wavefront as in the forward kernel.  For tap
 // offset d on an axis the source is t = q - d (periodic); under stride 2
-// only even t are images of coarse voxels, at t / 2.
-template <int STRIDE, int TAPS, int NB, int MT>
+// only even t are images of coarse voxels, at t / 2.  PAR (stride 2, W a
+// multiple of 32): a tile holds the 16 voxels x = 32 xb + 2 j + px of one
+// row, all of one parity on every axis, so whether a tap reaches the tile
+// is the same for all its voxels, and the wavefront skips the taps that
+// reach none of its tiles (3.4 of the 27 taps reach a tile on average; the
+// tiles of a wavefront share a row, so 6.75 taps reach one of them).
+template <int STRIDE, int TAPS, int NB, int MT, bool PAR = false>
 __global__ void __launch_bounds__(256)
 k_conv_dgrad(const uint16_t* __restrict__ dyp, const uint16_t* __restrict__ wt,
              float* __restrict__ dxp, int accumulate, Geom g) {
@@ -580,16 +585,34 @@ k_conv_dgrad(const uint16_t* __restrict__ dyp, const uint16_t* __restrict__ wt,
   int base[MT], oz[MT][3], oy[MT][3], ox[MT][3];
   uint32_t vz[MT], vy[MT], vx[MT];
   bool live[MT];
+  int64_t first[MT];  // PAR: the tile's first voxel; voxel j is first + 2 j
 #pragma unroll
   for (int m = 0; m < MT; ++m) {
     live[m] = q0 + 16 * m < g.m_in;
-    int64_t t = live[m] ? q0 + 16 * m + row : 0;
-    const int xq = (int)(t % g.W);
-    t /= g.W;
-    const int yq = (int)(t % g.H);
-    t /= g.H;
-    const int zq = (int)(t % g.D);
-    const int b = (int)(t / g.D);
+    int xq, yq, zq, b;
+    if (PAR) {
+      int64_t t = live[m] ? q0 / 16 + m : 0;  // tile index
+      const int px = (int)(t & 1);
+      t >>= 1;
+      const int xbs = g.W / 32;
+      const int xb = (int)(t % xbs);
+      t /= xbs;
+      yq = (int)(t % g.H);
+      t /= g.H;
+      zq = (int)(t % g.D);
+      b = (int)(t / g.D);
+      xq = xb * 32 + 2 * row + px;
+      first[m] = (((int64_t)b * g.D + zq) * g.H + yq) * g.W + xb * 32 + px;
+    } else {
+      int64_t t = live[m] ? q0 + 16 * m + row : 0;
+      xq = (int)(t % g.W);
+      t /= g.W;
+      yq = (int)(t % g.H);
+      t /= g.H;
+      zq = (int)(t % g.D);
+      b = (int)(t / g.D);
+      first[m] = 0;
+    }
     base[m] = b * g.Do * g.Ho * g.Wo;
     vz[m] = vy[m] = vx[m] = 0;
 #pragma unroll
@@ -602,6 +625,19 @@ k_conv_dgrad(const uint16_t* __restrict__ dyp, const uint16_t* __restrict__ wt,
       if (STRIDE == 1 || (ty & 1) == 0) vy[m] |= 1u << (d + 1);
       if (STRIDE == 1 || (tx & 1) == 0) vx[m] |= 1u << (d + 1);
     }
+  }
+  // PAR: the taps that reach a tile of the wavefront, one bit per tap (the
+  // same for every lane, as W is even and wrapping keeps the parity), held
+  // in a scalar register so that skipping a tap is a branch of the whole
+  // wavefront (a matrix instruction under a lane mask would still run)
+  uint32_t taps_run = 0;
+  if (PAR) {
+#pragma unroll
+    for (int tap = 0; tap < 27; ++tap)
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+        if ((vz[m] >> (tap / 9)) & (vy[m] >> ((tap / 3) % 3)) & (vx[m] >> (tap % 3)) & 1u) taps_run |= 1u << tap;
+    taps_run = __builtin_amdgcn_readfirstlane(taps_run);
   }
   f4 acc[MT][NB];
 #pragma unroll
@@ -620,6 +656,7 @@ k_conv_dgrad(const uint16_t* __restrict__ dyp, const uint16_t* __restrict__ wt,
       valid[m] = ((vz[m] >> iz) & (vy[m] >> iy) & (vx[m] >> ix) & 1u) != 0;
       ap[m] = dl + (int64_t)(base[m] + oz[m][iz] + oy[m][iy] + ox[m][ix]) * g.co;
     }
+    if (PAR && !((taps_run >> tap) & 1u)) continue;
     const uint16_t* bp = wt + ((int64_t)tap * g.ci + row) * g.co + 4 * kq;
     for (int c0 = 0; c0 < g.co; c0 += 16) {
       s4 a[MT], bv[NB];
@@ -642,7 +679,8 @@ k_conv_dgrad(const uint16_t* __restrict__ dyp, const uint16_t* __restrict__ wt,
       const int c = nb * 16 + row;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        float* o = dxp + (q0 + 16 * m + 4 * kq + r) * g.ci + c;
+        const int64_t v = PAR ? first[m] + 2 * (4 * kq + r) : q0 + 16 * m + 4 * kq + r;
+        float* o = dxp + v * g.ci + c;
         *o = accumulate ? *o + acc[m][nb][r] : acc[m][nb][r];
       }
     }
@@ -1515,14 +1553,14 @@ static bool launch_fwd_lds_s2(int nb, const uint16_t* x, const uint16_t* w, cons
   return true;
 }
 
-template <int STRIDE, int TAPS, int MT>
+template <int STRIDE, int TAPS, int MT, bool PAR>
 static void launch_dgrad_mt(int nb, const uint16_t* dy, const uint16_t* wt, float* dx, int acc,
                             const Geom& g, hipStream_t s) {
   const dim3 grid(pad_xcd(nblk(g.m_in / 16, 4 * MT))), block(256);
   switch (nb) {
 #define CASE(N)                                                                                   \
   case N:                                                                                         \
-    hipLaunchKernelGGL((k_conv_dgrad<STRIDE, TAPS, N, MT>), grid, block, 0, s, dy, wt, dx, acc, g); \
+    hipLaunchKernelGGL((k_conv_dgrad<STRIDE, TAPS, N, MT, PAR>), grid, block, 0, s, dy, wt, dx, acc, g); \
     break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
@@ -1532,10 +1570,20 @@ static void launch_dgrad_mt(int nb, const uint16_t* dy, const uint16_t* wt, floa
 template <int STRIDE, int TAPS>
 static void launch_dgrad_nb(int nb, const uint16_t* dy, const uint16_t* wt, float* dx, int acc,
                             const Geom& g, hipStream_t s) {
+  // stride 2 on rows of whole 32-voxel blocks: tiles of one parity class
+  constexpr bool kPar = STRIDE == 2 && TAPS == 27;
+  if (kPar && g.W % 32 == 0) {
+    switch (pick_mt(g.m_in)) {
+      case 4: launch_dgrad_mt<STRIDE, TAPS, 4, kPar>(nb, dy, wt, dx, acc, g, s); break;
+      case 2: launch_dgrad_mt<STRIDE, TAPS, 2, kPar>(nb, dy, wt, dx, acc, g, s); break;
+      default: launch_dgrad_mt<STRIDE, TAPS, 1, kPar>(nb, dy, wt, dx, acc, g, s); break;
+    }
+    return;
+  }
   switch (pick_mt(g.m_in)) {
-    case 4: launch_dgrad_mt<STRIDE, TAPS, 4>(nb, dy, wt, dx, acc, g, s); break;
-    case 2: launch_dgrad_mt<STRIDE, TAPS, 2>(nb, dy, wt, dx, acc, g, s); break;
-    default: launch_dgrad_mt<STRIDE, TAPS, 1>(nb, dy, wt, dx, acc, g, s); break;
+    case 4: launch_dgrad_mt<STRIDE, TAPS, 4, false>(nb, dy, wt, dx, acc, g, s); break;
+    case 2: launch_dgrad_mt<STRIDE, TAPS, 2, false>(nb, dy, wt, dx, acc, g, s); break;
+    default: launch_dgrad_mt<STRIDE, TAPS, 1, false>(nb, dy, wt, dx, acc, g, s); break;
   }
 }
 

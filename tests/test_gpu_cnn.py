@@ -118,7 +118,12 @@ def test_lrelu_bwd_bits(NN, n):
     assert torch.equal(out.cpu().view(torch.int16), ref.view(torch.int16))
 
 
-@pytest.mark.parametrize("case", CASES)
+# stride 2 on rows of whole 32-voxel blocks: the data gradient's tiles of
+# one parity class, with one, two and four tiles per wavefront
+GRAD_CASES = CASES + [(1, 32, 16, 32, 2, 27), (4, 32, 16, 16, 2, 27), (1, 64, 16, 32, 2, 27)]
+
+
+@pytest.mark.parametrize("case", GRAD_CASES)
 def test_conv_dgrad_wgrad(NN, case):
     B, n, ci, co, s, taps = case
     dev = torch.device("cuda")
