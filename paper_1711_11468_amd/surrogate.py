@@ -83,6 +83,19 @@ class UNet:
         self.t = 0
         rng = np.random.default_rng(seed)
         self.p = {}
+        # every parameter tensor, gradient, moment and bf16 copy is a view
+        # into one flat buffer of its kind (tensors start 64 elements
+        # apart at least, 16-byte aligned; the gaps stay zero), so one
+        # element-wise Adam launch updates the whole network
+        self._offsets = {}
+        total = 0
+        for L in self.layers:
+            nw = L.taps * L.c_out * L.c_in
+            self._offsets[L.name] = (total, total + -(-nw // 64) * 64)
+            total += -(-nw // 64) * 64 + -(-L.c_out // 64) * 64
+        d = self.device
+        self.flat = {k: torch.zeros(total, dtype=torch.float32, device=d) for k in ("p", "g", "m", "v")}
+        self.flat["p16"] = torch.zeros(total, dtype=torch.bfloat16, device=d)
         for L in self.layers:
             fan_in = L.taps * L.c_in
             std = math.sqrt(2.0 / fan_in) if L.act else 0.1 / math.sqrt(fan_in)
@@ -94,19 +107,20 @@ class UNet:
             self._add(L.name, w, np.zeros(L.c_out, np.float32))
 
     def _add(self, name, w, b):
-        torch = self.torch
-        d = self.device
-        wm = torch.from_numpy(w).to(d)
-        bm = torch.from_numpy(b).to(d)
-        self.p[name] = {
-            "w": wm, "b": bm,
-            "w16": torch.empty(wm.shape, dtype=torch.bfloat16, device=d),
-            "mw": torch.zeros_like(wm), "vw": torch.zeros_like(wm),
-            "mb": torch.zeros_like(bm), "vb": torch.zeros_like(bm),
-            "dw": torch.zeros_like(wm), "db": torch.zeros_like(bm),
-            "b16": torch.empty(bm.shape, dtype=torch.bfloat16, device=d),
-        }
-        nn.to_bf16(wm, self.p[name]["w16"])
+        ow, ob = self._offsets[name]
+        nw, nb = w.size, b.size
+        F = self.flat
+        q = {}
+        for key, buf, off, n, shape in (("w", "p", ow, nw, w.shape), ("b", "p", ob, nb, b.shape),
+                                        ("dw", "g", ow, nw, w.shape), ("db", "g", ob, nb, b.shape),
+                                        ("mw", "m", ow, nw, w.shape), ("mb", "m", ob, nb, b.shape),
+                                        ("vw", "v", ow, nw, w.shape), ("vb", "v", ob, nb, b.shape),
+                                        ("w16", "p16", ow, nw, w.shape), ("b16", "p16", ob, nb, b.shape)):
+            q[key] = F[buf][off:off + n].view(shape)
+        q["w"].copy_(self.torch.from_numpy(w))
+        q["b"].copy_(self.torch.from_numpy(b))
+        self.p[name] = q
+        nn.to_bf16(q["w"], q["w16"])
 
     # -- persistence ----------------------------------------------------------
     def state_dict(self):
@@ -282,10 +296,12 @@ class UNet:
         return b["loss"], b["dpre_head"]
 
     def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One Adam step of every parameter: a single launch over the flat
+        buffers (the update is element-wise, and the zero gaps between
+        tensors stay zero)."""
         self.t += 1
-        for name, q in self.p.items():
-            nn.adam_step(q["w"], q["dw"], q["mw"], q["vw"], q["w16"], lr, beta1, beta2, eps, self.t)
-            nn.adam_step(q["b"], q["db"], q["mb"], q["vb"], q["b16"], lr, beta1, beta2, eps, self.t)
+        F = self.flat
+        nn.adam_step(F["p"], F["g"], F["m"], F["v"], F["p16"], lr, beta1, beta2, eps, self.t)
 
     def train_step(self, mask_u8, target, batch, n, lr=1e-3):
         self.forward(mask_u8, batch, n)

@@ -187,6 +187,37 @@ def test_conv_fwd_upcat_equals_concat_then_conv(NN, B, n, c1, c2, co):
         NN.conv_fwd_upcat(NN.desc(1, n, n, n, ci, co, stride=2), coarse, c1, skip, w, b, got)
 
 
+def test_unet_flat_adam_equals_per_tensor(NN):
+    """The network's single Adam launch over its flat parameter buffers
+    gives the bits of one nn_adam_step call per tensor, over three steps,
+    and leaves the gaps between tensors at zero."""
+    from paper_1711_11468_amd.surrogate import UNet
+    dev = torch.device("cuda")
+    net = UNet(device=dev, seed=9)
+    g = torch.Generator().manual_seed(31)
+    ref = {}
+    for k, q in net.p.items():
+        ref[k] = {key: q[key].clone() for key in ("w", "b", "mw", "vw", "mb", "vb", "w16", "b16")}
+    for step in range(1, 4):
+        for k, q in net.p.items():
+            q["dw"].copy_(torch.randn(q["dw"].shape, generator=g) * 0.01)
+            q["db"].copy_(torch.randn(q["db"].shape, generator=g) * 0.01)
+            r = ref[k]
+            NN.adam_step(r["w"], q["dw"], r["mw"], r["vw"], r["w16"], 2e-3, 0.9, 0.999, 1e-8, step)
+            NN.adam_step(r["b"], q["db"], r["mb"], r["vb"], r["b16"], 2e-3, 0.9, 0.999, 1e-8, step)
+        net.adam(2e-3)
+    for k, q in net.p.items():
+        for key in ("w", "b", "mw", "vw", "mb", "vb"):
+            assert torch.equal(q[key], ref[k][key]), (k, key)
+        for key in ("w16", "b16"):
+            assert torch.equal(q[key].view(torch.int16), ref[k][key].view(torch.int16)), (k, key)
+    used = torch.zeros(net.flat["p"].numel(), dtype=torch.bool, device=dev)
+    for k, (ow, ob) in net._offsets.items():
+        used[ow:ow + net.p[k]["w"].numel()] = True
+        used[ob:ob + net.p[k]["b"].numel()] = True
+    assert int(torch.count_nonzero(net.flat["p"][~used])) == 0
+
+
 def test_unet_fused_concat_same_output(NN):
     """The network's inference path (decoder inputs not concatenated) gives
     the same output bits as the training path."""
