@@ -846,7 +846,7 @@ k_conv_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dyp,
   }
 }
 
-// Weight gradient of stride-1 3x3x3 layers with 16 or 32 output channels on
+// Weight gradient of stride-1 3x3x3 layers with 16, 32 or 64 output channels on
 // grids of 16 x 4 x 4 bricks (the LDS forward's tiles).  A workgroup owns a
 // range of bricks and one 16-channel input block (grid y); per brick it
 // stages the brick's dy, transposed to [channel][voxel], and its 18 x 6 x 6 input halo,
@@ -1753,7 +1753,7 @@ int nn_conv3d_wgrad(const nn_conv_desc* d, const uint16_t* x, const uint16_t* dy
   size_t lds;
   wgrad_plan(d, &tpb, &tpw, &lds);
   float* bp = db ? workspace + nw : nullptr;
-  const bool brick = d->taps == 27 && d->stride == 1 && (d->c_out == 16 || d->c_out == 32) &&
+  const bool brick = d->taps == 27 && d->stride == 1 && (d->c_out == 16 || d->c_out == 32 || d->c_out == 64) &&
                      g.W % kLdsTX == 0 && g.H % kLdsTY == 0 && g.D % kLdsTZ == 0 &&
                      ((uintptr_t)x & 15) == 0 && ((uintptr_t)dy & 15) == 0;
   if (brick) {
@@ -1762,8 +1762,10 @@ int nn_conv3d_wgrad(const nn_conv_desc* d, const uint16_t* x, const uint16_t* dy
     const dim3 grid(pad_xcd((unsigned)chunks), d->c_in / 16), block(kWbThreads);
     if (d->c_out == 16)
       hipLaunchKernelGGL(k_conv_wgrad_brick<1>, grid, block, 0, s, x, dy, workspace, chunks, per, db ? 1 : 0, g);
-    else
+    else if (d->c_out == 32)
       hipLaunchKernelGGL(k_conv_wgrad_brick<2>, grid, block, 0, s, x, dy, workspace, chunks, per, db ? 1 : 0, g);
+    else
+      hipLaunchKernelGGL(k_conv_wgrad_brick<4>, grid, block, 0, s, x, dy, workspace, chunks, per, db ? 1 : 0, g);
   } else if (d->taps == 1) launch_wgrad_tpw<1, 1>(tpw, tpb, lds, x, dy, workspace, bp, chunk, chunks, g, s);
   else if (d->stride == 1) launch_wgrad_tpw<1, 27>(tpw, tpb, lds, x, dy, workspace, bp, chunk, chunks, g, s);
   else launch_wgrad_tpw<2, 27>(tpw, tpb, lds, x, dy, workspace, bp, chunk, chunks, g, s);

@@ -119,8 +119,10 @@ def test_lrelu_bwd_bits(NN, n):
 
 
 # stride 2 on rows of whole 32-voxel blocks: the data gradient's tiles of
-# one parity class, with one, two and four tiles per wavefront
-GRAD_CASES = CASES + [(1, 32, 16, 32, 2, 27), (4, 32, 16, 16, 2, 27), (1, 64, 16, 32, 2, 27)]
+# one parity class, with one, two and four tiles per wavefront; 64 outputs
+# on tiled grids (the brick weight gradient with four output blocks)
+GRAD_CASES = CASES + [(1, 32, 16, 32, 2, 27), (4, 32, 16, 16, 2, 27), (1, 64, 16, 32, 2, 27),
+                      (1, 16, 32, 64, 1, 27), (2, 16, 64, 64, 1, 27)]
 
 
 @pytest.mark.parametrize("case", GRAD_CASES)
