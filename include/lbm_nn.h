@@ -71,7 +71,10 @@ int nn_conv3d_fwd_upcat(const nn_conv_desc* d, const uint16_t* coarse, int32_t c
  * input of the convolution given dy, the gradient with respect to its
  * pre-activation output ([B][D/s][H/s][W/s][c_out] bf16).  dx: [B][D][H][W]
  * [c_in] float32; accumulate != 0 adds to dx.  w_t: workspace of
- * taps*c_in*c_out bf16 (the transposed weights). */
+ * taps*c_in*c_out bf16, left holding the transposed weights (for stride-1
+ * 3x3x3 layers on grids with W % 16, H % 4 and D % 4 == 0, dy and w_t
+ * 16-byte aligned, also mirrored through the centre tap); its contents are
+ * scratch, not part of the result. */
 int nn_conv3d_dgrad(const nn_conv_desc* d, const uint16_t* dy, const uint16_t* w,
                     uint16_t* w_t, float* dx, int32_t accumulate, void* stream);
 
