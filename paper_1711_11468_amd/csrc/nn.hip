@@ -574,10 +574,13 @@ __global__ void k_conv1x1_few(const uint16_t* __restrict__ x, const uint16_t* __
 template <int STRIDE, int TAPS, int NB, int MT, bool PAR = false>
 __global__ void __launch_bounds__(256)
 k_conv_dgrad(const uint16_t* __restrict__ dyp, const uint16_t* __restrict__ wt,
-             float* __restrict__ dxp, int accumulate, Geom g) {
+             float* __restrict__ dxp, int accumulate, int nsplit, Geom g) {
   const int lane = threadIdx.x & 63;
   const int64_t blk = xcd_tile(blockIdx.x, gridDim.x);
-  const int64_t q0 = (blk * 4 + (threadIdx.x >> 6)) * 16 * MT;
+  // small grids split the output blocks over nsplit wavefronts per tile group
+  const int64_t wv = blk * 4 + (threadIdx.x >> 6);
+  const int cb0 = (int)(wv % nsplit) * NB * 16;  // first output channel of the wavefront
+  const int64_t q0 = (wv / nsplit) * 16 * MT;
   if (q0 >= g.m_in) return;
   const int row = lane & 15, kq = lane >> 4;
   // per tile: coarse-grid voxel offsets of the sources at d = -1, 0, +1 on
@@ -657,7 +660,7 @@ k_conv_dgrad(const uint16_t* __restrict__ dyp, const uint16_t* __restrict__ wt,
       ap[m] = dl + (int64_t)(base[m] + oz[m][iz] + oy[m][iy] + ox[m][ix]) * g.co;
     }
     if (PAR && !((taps_run >> tap) & 1u)) continue;
-    const uint16_t* bp = wt + ((int64_t)tap * g.ci + row) * g.co + 4 * kq;
+    const uint16_t* bp = wt + ((int64_t)tap * g.ci + cb0 + row) * g.co + 4 * kq;
     for (int c0 = 0; c0 < g.co; c0 += 16) {
       s4 a[MT], bv[NB];
 #pragma unroll
@@ -676,7 +679,7 @@ k_conv_dgrad(const uint16_t* __restrict__ dyp, const uint16_t* __restrict__ wt,
     if (!live[m]) continue;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const int c = nb * 16 + row;
+      const int c = cb0 + nb * 16 + row;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t v = PAR ? first[m] + 2 * (4 * kq + r) : q0 + 16 * m + 4 * kq + r;
@@ -1556,11 +1559,16 @@ static bool launch_fwd_lds_s2(int nb, const uint16_t* x, const uint16_t* w, cons
 template <int STRIDE, int TAPS, int MT, bool PAR>
 static void launch_dgrad_mt(int nb, const uint16_t* dy, const uint16_t* wt, float* dx, int acc,
                             const Geom& g, hipStream_t s) {
-  const dim3 grid(pad_xcd(nblk(g.m_in / 16, 4 * MT))), block(256);
-  switch (nb) {
+  // grids with fewer than 4096 wavefronts split the output blocks
+  int nsplit = 1;
+  while (nsplit < nb && nb % (2 * nsplit) == 0 && (int64_t)nblk(g.m_in / 16, MT) * nsplit < 4096)
+    nsplit *= 2;
+  const dim3 grid(pad_xcd(nblk(nblk(g.m_in / 16, MT) * nsplit, 4))), block(256);
+  switch (nb / nsplit) {
 #define CASE(N)                                                                                   \
   case N:                                                                                         \
-    hipLaunchKernelGGL((k_conv_dgrad<STRIDE, TAPS, N, MT, PAR>), grid, block, 0, s, dy, wt, dx, acc, g); \
+    hipLaunchKernelGGL((k_conv_dgrad<STRIDE, TAPS, N, MT, PAR>), grid, block, 0, s, dy, wt, dx, acc, \
+                       nsplit, g);                                                                \
     break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
