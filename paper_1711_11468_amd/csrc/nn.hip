@@ -1,8 +1,11 @@
 // nn.hip - BF16 MFMA kernels of the learned warm start (ABI: include/lbm_nn.h).
 //
-// Convolutions are implicit GEMMs.  The stride-1 3x3x3 forward on tileable
-// grids runs through LDS on v_mfma_f32_16x16x32_bf16 (k_conv_fwd_lds below);
-// the other forms use v_mfma_f32_16x16x16_bf16, where one wavefront
+// Convolutions are implicit GEMMs.  On grids of 16 x 4 x 4 tiles the
+// stride-1 and stride-2 3x3x3 forwards, the stride-1 data gradient (the
+// forward of dy with mirrored, transposed weights) and the stride-1 weight
+// gradient run through LDS on v_mfma_f32_16x16x32_bf16 (k_conv_fwd_lds,
+// k_conv_fwd_lds_s2, k_conv_wgrad_brick below); the other forms use
+// v_mfma_f32_16x16x16_bf16, where one wavefront
 // owns a 16 x 16 tile of the (voxel x channel) output and walks the K
 // dimension (taps x input-channel chunks of 16).  Operand layout of the
 // instruction (64 lanes, l = lane): A[i][k] lives in lane i + 16*(k/4),
