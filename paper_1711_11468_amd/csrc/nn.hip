@@ -1,6 +1,7 @@
 // nn.hip - BF16 MFMA kernels of the learned warm start (ABI: include/lbm_nn.h).
 //
-// Convolutions are implicit GEMMs.  On grids of 16 x 4 x 4 tiles the
+// Convolutions are implicit GEMMs.  On grids that their LDS tiles cover
+// (16 x 4 x 4 voxels; 16 x 2 x 4 outputs under stride 2) the
 // stride-1 and stride-2 3x3x3 forwards, the stride-1 data gradient (the
 // forward of dy with mirrored, transposed weights) and the stride-1 weight
 // gradient run through LDS on v_mfma_f32_16x16x32_bf16 (k_conv_fwd_lds,
